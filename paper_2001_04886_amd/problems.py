@@ -1,0 +1,166 @@
+"""Seeded synthetic problem generators (inputs only; no solver arithmetic).
+
+This module is shared by the tests, the benchmark and the oracle checks.  It
+builds the *inputs* of a solve -- stencil coefficients of the discretised PDE,
+seeded exact solutions, random fields, batched system tables -- and nothing
+of the s-step methods themselves.  It imports neither the GPU binding nor the
+oracle.
+
+Problems
+--------
+* Convection-diffusion ``-Lap u + gamma * (u_x + u_y [+ u_z]) = f`` on the unit
+  square / cube, Dirichlet 0, 5-point (2-D) or 7-point (3-D) centred
+  differences on an ``n``-point-per-axis interior grid, ``h = 1/(n+1)``: the
+  same discretisation as the paper's Sec. 5 (five-point Laplacian, central
+  first derivatives) with constant coefficients.
+* Variable-coefficient diffusion ``-div(k grad u) = f`` (harmonic-mean face
+  coefficients) for the learned-initial-guess problem.
+* Exact solutions ``x_true[p] = 2 U(seed, p) - 1`` with ``U`` the top 53 bits of
+  SplitMix64 applied to the counter ``seed * 2**40 + p`` (a counter-based
+  generator, so any slice can be produced independently on any device).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function of state ``z`` (Steele, Lea & Flood 2014):
+    z += golden gamma, then two xor-shift-multiply rounds and a final xor-shift.
+    Vectorised over a uint64 array; arithmetic wraps mod 2**64."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = z + _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """U(seed, p) in [0, 1) for p = offset .. offset+n-1, 53-bit resolution."""
+    ctr = np.uint64(seed) * np.uint64(1 << 40) + np.arange(offset, offset + n, dtype=np.uint64)
+    return (splitmix64(ctr) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def x_true(seed: int, n: int) -> np.ndarray:
+    """Seeded exact solution, entries uniform in [-1, 1)."""
+    return 2.0 * uniform01(seed, n) - 1.0
+
+
+def convdiff_coeffs(ndim: int, nx: int, ny: int, nz: int = 1, gamma: float = 0.0):
+    """Seven stencil coefficients (centre, -x, +x, -y, +y, -z, +z) of
+    -Lap u + gamma * sum_d du/dx_d with h_d = 1/(n_d + 1)."""
+    ns = [nx, ny] + ([nz] if ndim == 3 else [])
+    c = np.zeros(7)
+    for d, n in enumerate(ns):
+        h = 1.0 / (n + 1)
+        c[0] += 2.0 / h**2
+        c[1 + 2 * d] = -1.0 / h**2 - gamma / (2.0 * h)
+        c[2 + 2 * d] = -1.0 / h**2 + gamma / (2.0 * h)
+    return c
+
+
+class Problem:
+    """A stencil problem: grid, coefficients (constant ``c`` or per-point
+    ``coef`` [7][N]), seeded exact solution."""
+
+    def __init__(self, ndim, nx, ny, nz=1, c=None, coef=None, seed=0, name=""):
+        self.ndim, self.nx, self.ny = int(ndim), int(nx), int(ny)
+        self.nz = int(nz) if ndim == 3 else 1
+        self.c = np.zeros(7) if c is None else np.asarray(c, dtype=np.float64)
+        self.coef = coef
+        self.seed = seed
+        self.name = name
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def x_true(self) -> np.ndarray:
+        return x_true(self.seed, self.N)
+
+
+def convdiff(ndim: int, n: int, gamma: float, seed: int = 0, ny: int | None = None,
+             nz: int | None = None) -> Problem:
+    ny = n if ny is None else ny
+    nz = (n if nz is None else nz) if ndim == 3 else 1
+    return Problem(ndim, n, ny, nz, c=convdiff_coeffs(ndim, n, ny, nz, gamma), seed=seed,
+                   name=f"convdiff{ndim}d_{n}_g{gamma:g}")
+
+
+# Named workloads -----------------------------------------------------------
+
+def small_2d(seed: int = 0) -> Problem:
+    """64 x 64 interior grid, gamma = 10 (N = 4096)."""
+    return convdiff(2, 64, 10.0, seed)
+
+
+def cube_3d(n: int = 256, seed: int = 0, gamma: float = 50.0) -> Problem:
+    """n^3 interior grid, 7-point, gamma = 50 (n = 256: N = 16 777 216)."""
+    return convdiff(3, n, gamma, seed)
+
+
+def square_2d_large(n: int = 4096, seed: int = 0, gamma: float = 50.0) -> Problem:
+    """n^2 interior grid, 5-point, gamma = 50 (n = 4096: N = 16 777 216)."""
+    return convdiff(2, n, gamma, seed)
+
+
+def batched_table(nsys: int = 512, master_seed: int = 0, nmin: int = 32, nmax: int = 512,
+                  gmax: float = 100.0):
+    """Per-system (side length n ~ U{nmin..nmax}, gamma ~ U(0, gmax), seed) for
+    a batch of independent 2-D convection-diffusion systems, all drawn from the
+    counter-based generator with ``master_seed``."""
+    u = uniform01(master_seed + 7919, 2 * nsys)
+    ns = nmin + np.minimum((u[:nsys] * (nmax - nmin + 1)).astype(np.int64), nmax - nmin)
+    gammas = u[nsys:] * gmax
+    return [(int(ns[i]), float(gammas[i]), int(master_seed * 100003 + i + 1)) for i in range(nsys)]
+
+
+# Gaussian random fields ----------------------------------------------------
+
+def grf(n: int, length: float, seed: int, pad: int = 2) -> np.ndarray:
+    """Unit-variance Gaussian random field on an n x n grid of the unit square
+    with covariance exp(-r^2 / (2 length^2)), by spectral synthesis on a
+    (pad*n)^2 periodic grid cropped to n x n (the crop avoids wrap-around
+    correlation).  Row index = y, column index = x."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = pad * n
+    h = 1.0 / (n + 1)
+    k = np.fft.fftfreq(m, d=h) * 2.0 * np.pi
+    kx, ky = np.meshgrid(k, k, indexing="xy")
+    # spectral density of the squared-exponential covariance (2-D)
+    spec = np.exp(-0.5 * (kx**2 + ky**2) * length**2)
+    noise = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    field = np.fft.ifft2(noise * np.sqrt(spec)).real
+    field = field[:n, :n]
+    field = (field - field.mean()) / field.std()
+    return np.ascontiguousarray(field)
+
+
+def diffusion_coef(logk: np.ndarray) -> np.ndarray:
+    """Per-point [7][N] stencil of -div(k grad u) on an n x n grid, h = 1/(n+1),
+    with harmonic-mean face coefficients k_{i+1/2} = 2 k_i k_{i+1}/(k_i + k_{i+1});
+    faces on the boundary use the cell's own k (Dirichlet 0 outside)."""
+    ny, nx = logk.shape
+    k = np.exp(logk)
+    h2 = (1.0 / (nx + 1)) ** 2
+
+    def hm(a, b):
+        return 2.0 * a * b / (a + b)
+
+    kw = np.empty_like(k); ke = np.empty_like(k); ks = np.empty_like(k); kn = np.empty_like(k)
+    kw[:, 1:] = hm(k[:, 1:], k[:, :-1]); kw[:, 0] = k[:, 0]
+    ke[:, :-1] = hm(k[:, :-1], k[:, 1:]); ke[:, -1] = k[:, -1]
+    ks[1:, :] = hm(k[1:, :], k[:-1, :]); ks[0, :] = k[0, :]
+    kn[:-1, :] = hm(k[:-1, :], k[1:, :]); kn[-1, :] = k[-1, :]
+    coef = np.zeros((7, nx * ny))
+    coef[0] = ((kw + ke + ks + kn) / h2).ravel()
+    coef[1] = (-kw / h2).ravel()
+    coef[2] = (-ke / h2).ravel()
+    coef[3] = (-ks / h2).ravel()
+    coef[4] = (-kn / h2).ravel()
+    return coef
