@@ -1,0 +1,190 @@
+/*
+ * sstep.h -- C ABI of the MI355X (gfx950) s-step Krylov solver library
+ * (libsstep.so).
+ *
+ * Methods (Chronopoulos & Kim, "s-Step Orthomin and GMRES implemented on
+ * parallel computers", arXiv 2001.04886):
+ *   - s-step Orthomin(k)   (Sec. 3, Alg. 3.1)
+ *   - s-step GMRES(m)      (Sec. 4, Alg. 4.1 s-step Arnoldi, eqs. (4)-(8),
+ *                           Alg. 4.2 restarted s-step GMRES)
+ * for the linear system A x = f (Sec. 1, eq. (1)) with A a matrix-free
+ * 5-point (2-D) or 7-point (3-D) finite-difference stencil (Sec. 1 and 5).
+ *
+ * Conventions that hold for every entry point:
+ *   - Every N-length array is a DEVICE pointer owned by the caller, FP64,
+ *     contiguous, x-fastest lexicographic order p = i + nx*(j + ny*l).
+ *     The library never frees caller memory and keeps no pointer after the
+ *     call returns.
+ *   - Host structs are read only during the call.
+ *   - All GPU work is enqueued on opt->stream (a hipStream_t; NULL = the
+ *     default stream).  Solver entry points return after the work has
+ *     completed; primitives (sstep_stencil_apply, sstep_kernel_*) only
+ *     enqueue and return.
+ *   - Return value: a status code (sstep_status); also written to
+ *     info->status when info is given.  Arguments are validated before any
+ *     launch.  No exception crosses the boundary.
+ *   - Calls on different streams are independent; the library holds no
+ *     mutable global state besides a lazily created per-device stream-less
+ *     kernel configuration.
+ */
+#ifndef SSTEP_H
+#define SSTEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSTEP_OK = 0,               /* converged: ||f - A x|| <= tol ||f|| (true residual, FP64) */
+    SSTEP_NOT_CONVERGED = 1,    /* iteration cap reached; x holds the last iterate          */
+    SSTEP_ERR_ARG = -1,         /* invalid argument; nothing was launched                   */
+    SSTEP_ERR_BREAKDOWN = -2,   /* s-Omin: Gram matrix W_i of a direction block is zero     */
+    SSTEP_ERR_NONFINITE = -3,   /* NaN / Inf in a residual or estimate; x holds the last
+                                   finite iterate of the previous restart                    */
+    SSTEP_ERR_HIP = -4,         /* a HIP runtime call failed                                 */
+    SSTEP_ERR_NOMEM = -5        /* workspace too small / allocation failed                   */
+} sstep_status;
+
+/* Matrix-free stencil operator A (Sec. 1, Sec. 5).
+ * Row p of A x sums c[q] * x[neighbour q] over the neighbours inside the grid
+ * (neighbours outside are dropped: homogeneous Dirichlet) plus c[0] * x[p].
+ * Coefficient order: 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.
+ * If coef != NULL it is a DEVICE array [7][N] of per-point coefficients in
+ * the same order (variable coefficients) and c[] is ignored. */
+typedef struct {
+    int32_t ndim;               /* 2 or 3                                         */
+    int32_t nx, ny, nz;         /* interior points per axis; nz ignored for ndim 2 */
+    double c[7];
+    const double *coef;         /* optional DEVICE [7][N]                          */
+} sstep_stencil;
+
+enum { SSTEP_BASIS_MONOMIAL = 0, SSTEP_BASIS_CHEBYSHEV = 1 };
+enum { SSTEP_FP64 = 0, SSTEP_MIXED = 1 };
+enum { SSTEP_METHOD_OMIN = 0, SSTEP_METHOD_GMRES = 1 };
+
+typedef struct {
+    int32_t max_iters;    /* s-Omin: s-step iterations; s-GMRES: s-blocks over all cycles;
+                             0 = 10000                                                     */
+    int32_t precision;    /* SSTEP_FP64, or SSTEP_MIXED (s-GMRES only): basis vectors,
+                             matrix powers and block updates in FP32; Gram matrices,
+                             small solves, Hessenberg least squares, x and the restart
+                             residual in FP64 (iterative refinement by restarts)           */
+    int32_t basis;        /* SSTEP_BASIS_MONOMIAL (y_j = A y_{j-1} / sigma) or
+                             SSTEP_BASIS_CHEBYSHEV (same Krylov span, better conditioned)  */
+    int32_t profile;      /* 1: time each kernel class with HIP events into info           */
+    double sigma;         /* power scaling; 0 = smallest power of two >= Gershgorin bound */
+    double inner_tol;     /* SSTEP_MIXED: a cycle stops once its least-squares residual
+                             falls below inner_tol * (its starting residual); 0 = 1e-5     */
+    void *workspace;      /* optional caller-owned DEVICE workspace (256-byte aligned) of
+                             at least sstep_workspace_bytes(); NULL = allocated per call  */
+    size_t workspace_bytes;
+    void *stream;         /* hipStream_t                                                   */
+} sstep_options;
+
+/* kernel classes reported in sstep_info (index into the arrays below) */
+enum {
+    SSTEP_K_MPK = 0,      /* matrix powers                     */
+    SSTEP_K_GRAM = 1,     /* block Gram (all inner products)   */
+    SSTEP_K_UPDATE = 2,   /* block updates / assembly          */
+    SSTEP_K_RESID = 3,    /* true residual r = f - A x         */
+    SSTEP_K_SCALAR = 4,   /* small FP64 solves and reductions  */
+    SSTEP_K_NCLASS = 5
+};
+
+typedef struct {
+    int32_t status;
+    int32_t iters;        /* s-Omin: s-step iterations; s-GMRES: s-blocks built            */
+    int32_t cycles;       /* s-GMRES: restart cycles; s-Omin: recurrence restarts + 1     */
+    int32_t matvecs;      /* applications of A                                             */
+    double rel_resid;     /* true ||f - A x|| / ||f|| at exit (FP64)                       */
+    double rel_resid_est; /* last least-squares / recurrence estimate / ||f||              */
+    double sigma;         /* scaling used                                                  */
+    double cheb_centre, cheb_half_width;   /* Chebyshev interval used (basis 1)            */
+    double ms_total;      /* wall time of the call (HIP events on the stream)              */
+    /* with profile = 1: per kernel class launches, summed duration and the
+       algorithmic bytes (each vector element read or written once) */
+    int64_t launches[SSTEP_K_NCLASS];
+    double ms[SSTEP_K_NCLASS];
+    double bytes[SSTEP_K_NCLASS];
+} sstep_info;
+
+/* Fill *opt with the defaults (all zero / NULL). */
+void sstep_default_options(sstep_options *opt);
+
+/* Human-readable name of a status code (static string). */
+const char *sstep_status_string(int status);
+
+/* Device workspace (bytes) a solve needs for this operator and parameters.
+ * method: SSTEP_METHOD_OMIN (k_or_m = k) or SSTEP_METHOD_GMRES (k_or_m = m).
+ * Returns 0 for invalid arguments. */
+size_t sstep_workspace_bytes(const sstep_stencil *A, int method, int s, int k_or_m,
+                             int precision);
+
+/* Restarted s-step GMRES(m) (Sec. 4, Alg. 4.2).  Solves A x = f.
+ *   f   : DEVICE [N] right-hand side (read only)
+ *   x   : DEVICE [N] initial guess x0 on entry, solution on exit
+ *   s   : block size, 1 <= s <= 16 (s = 1 is standard GMRES(m))
+ *   m   : s-blocks per restart cycle, 1 <= m; Krylov dimension m*s <= 2048
+ *   tol : relative tolerance on the true residual, >= 0
+ * One cycle: r0 = f - A x0, w_1 = r0/||r0||; per block k the matrix powers
+ * of w_k, one Gram of all inner products against the previous blocks, the
+ * block update (Scalar1/Scalar2 solved on the device in FP64), the next
+ * normalised start vector w_{k+1}, one Hessenberg block column and its Givens
+ * rotations; exit at m blocks, when the least-squares residual reaches tol, or
+ * on breakdown; x = x0 + V y (eq. (8)).  Returns SSTEP_OK, SSTEP_NOT_CONVERGED
+ * (max_iters blocks built) or an error. */
+int sstep_gmres_solve(const sstep_stencil *A, const double *f, double *x, int s, int m,
+                      double tol, const sstep_options *opt, sstep_info *info);
+
+/* s-step Orthomin(k) (Sec. 3, Alg. 3.1).  Solves A x = f.
+ *   s : block size 1..16 (s = 1 is Omin(k));  k : window of previous
+ *   direction blocks, 1 <= k <= 64 (k >= iterations gives s-step GCR).
+ * Per iteration: W_i = AP_i^T AP_i, m_i = AP_i^T r_i, a_i = W_i^{-1} m_i,
+ * x += P_i a_i, r -= AP_i a_i; matrix powers of r give R, AR; C_j = AP_j^T AR,
+ * B_j = -W_j^{-1} C_j; P_{i+1} = R + sum P_j B_j, AP_{i+1} = AR + sum AP_j B_j.
+ * The recurrence residual triggers a true-residual check; on failure r is
+ * replaced by the true residual and the window restarts.
+ * precision must be SSTEP_FP64. */
+int sstep_omin_solve(const sstep_stencil *A, const double *f, double *x, int s, int k,
+                     double tol, const sstep_options *opt, sstep_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* Primitives (the building blocks of the solvers; enqueue only)           */
+/* ---------------------------------------------------------------------- */
+
+/* y = A x (Sec. 1 operator).  x, y DEVICE [N], must not alias. */
+int sstep_stencil_apply(const sstep_stencil *A, const double *x, double *y, void *stream);
+
+/* Matrix-powers kernel (Sec. 3-4: the s directions from one vector).
+ * Y: DEVICE, s+1 columns of N doubles with column stride ldy >= N; column 0
+ * is the input w (read), columns 1..s are written:
+ *   basis 0: y_0 = w * in_scale, y_j = A y_{j-1} / sigma
+ *   basis 1: y_1 = (A - c) y_0 / d, y_{j+1} = 2 (A - c) y_j / d - y_{j-1}
+ * Column 0 itself is not rewritten (it keeps w; y_0 is w * in_scale). */
+int sstep_kernel_mpk(const sstep_stencil *A, double *Y, int64_t ldy, int s, int basis,
+                     double in_scale, double sigma, double cheb_c, double cheb_d,
+                     void *stream);
+
+/* Block Gram G = X^T Z accumulated in FP64 with a fixed reduction order
+ * (Sec. 3-4: all inner products of one s-step at once).
+ *   X: DEVICE, ncx columns of N doubles, stride ldx;  Z: DEVICE, ncz <= 16
+ *   columns, stride ldz;  G: DEVICE ncx x ncz, row-major (G[c*ncz + j]).
+ * The result is deterministic for fixed (N, ncx, ncz). */
+int sstep_kernel_gram(const double *X, int64_t ldx, int ncx, const double *Z, int64_t ldz,
+                      int ncz, int64_t N, double *G, void *stream);
+
+/* Block update Y[:, l] += sum_c X[:, c] * M[c*ncy + l]  (l < ncy <= 16)
+ * (Sec. 3-4 linear combinations).  X: DEVICE ncx columns, stride ldx;
+ * Y: DEVICE ncy columns, stride ldy (updated in place; may not overlap X);
+ * M: DEVICE ncx x ncy row-major FP64 coefficients.  X and M may be NULL when
+ * ncx == 0. */
+int sstep_kernel_update(const double *X, int64_t ldx, int ncx, double *Y, int64_t ldy,
+                        int ncy, const double *M, int64_t N, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,242 @@
+// capi.hip -- extern "C" entry points of libsstep.so: argument validation,
+// workspace handling, timing, and the primitive kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/sstep.h"
+#include "dense.hpp"
+#include "launch.hpp"
+#include "solvers.hpp"
+
+using namespace sstep;
+
+namespace {
+
+bool stencil_ok(const sstep_stencil* A) {
+    if (!A) return false;
+    if (A->ndim != 2 && A->ndim != 3) return false;
+    if (A->nx < 1 || A->ny < 1 || (A->ndim == 3 && A->nz < 1)) return false;
+    const long long N = grid_points(*A);
+    if (N > (1LL << 31) - 1) return false;
+    if (!A->coef)
+        for (int q = 0; q < 2 * A->ndim + 1; ++q)
+            if (!std::isfinite(A->c[q])) return false;
+    // rows of the grid are addressed by blockIdx (one workgroup per row segment)
+    const long long rows = (long long)A->ny * (A->ndim == 3 ? A->nz : 1) * ((A->nx + 255) / 256);
+    if (rows > 0x7fffffffLL) return false;
+    return true;
+}
+
+int set_status(sstep_info* info, int st) {
+    if (info) info->status = st;
+    return st;
+}
+
+template <typename F>
+int guarded(sstep_info* info, F&& fn) {
+    try {
+        return set_status(info, fn());
+    } catch (const HipFailure&) {
+        (void)hipGetLastError();
+        return set_status(info, SSTEP_ERR_HIP);
+    }
+}
+
+// Run a solver with workspace handling and total timing.
+template <typename Solve>
+int run_solver(const sstep_options* opt_in, size_t need, sstep_info* info, Solve&& solve) {
+    sstep_options opt;
+    if (opt_in) opt = *opt_in;
+    else sstep_default_options(&opt);
+    if (info) std::memset(info, 0, sizeof(*info));
+    return guarded(info, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)opt.stream;
+        c.profile = opt.profile != 0;
+        void* ws = opt.workspace;
+        size_t wsb = opt.workspace_bytes;
+        bool owned = false;
+        if (!ws) {
+            if (hipMalloc(&ws, need) != hipSuccess) {
+                (void)hipGetLastError();
+                return SSTEP_ERR_NOMEM;
+            }
+            wsb = need;
+            owned = true;
+        } else if (wsb < need || ((uintptr_t)ws & 255u)) {
+            return SSTEP_ERR_NOMEM;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int st = SSTEP_ERR_HIP;
+        try {
+            SSTEP_HIP(hipEventCreate(&e0));
+            SSTEP_HIP(hipEventCreate(&e1));
+            SSTEP_HIP(hipEventRecord(e0, c.st));
+            st = solve(c, opt, ws, wsb);
+            SSTEP_HIP(hipEventRecord(e1, c.st));
+            SSTEP_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            SSTEP_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (info) {
+                info->ms_total = ms;
+                for (int k = 0; k < SSTEP_K_NCLASS; ++k) {
+                    info->launches[k] = c.launches[k];
+                    info->ms[k] = c.ms[k];
+                    info->bytes[k] = c.bytes[k];
+                }
+            }
+        } catch (...) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (owned) (void)hipFree(ws);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (owned) SSTEP_HIP(hipFree(ws));
+        return st;
+    });
+}
+
+}  // namespace
+
+extern "C" {
+
+void sstep_default_options(sstep_options* opt) {
+    if (opt) std::memset(opt, 0, sizeof(*opt));
+}
+
+const char* sstep_status_string(int status) {
+    switch (status) {
+        case SSTEP_OK: return "converged";
+        case SSTEP_NOT_CONVERGED: return "not converged (iteration cap)";
+        case SSTEP_ERR_ARG: return "invalid argument";
+        case SSTEP_ERR_BREAKDOWN: return "breakdown (singular Gram matrix)";
+        case SSTEP_ERR_NONFINITE: return "non-finite value";
+        case SSTEP_ERR_HIP: return "HIP runtime error";
+        case SSTEP_ERR_NOMEM: return "out of memory / workspace too small";
+        default: return "unknown status";
+    }
+}
+
+size_t sstep_workspace_bytes(const sstep_stencil* A, int method, int s, int k_or_m,
+                             int precision) {
+    if (!stencil_ok(A) || s < 1 || s > kMaxS || k_or_m < 1) return 0;
+    if (method == SSTEP_METHOD_GMRES) {
+        if ((long long)k_or_m * s > 2048) return 0;
+        if (precision != SSTEP_FP64 && precision != SSTEP_MIXED) return 0;
+        return gmres_workspace_bytes(*A, s, k_or_m, precision);
+    }
+    if (method == SSTEP_METHOD_OMIN) {
+        if (k_or_m > 64 || precision != SSTEP_FP64) return 0;
+        return omin_workspace_bytes(*A, s, k_or_m);
+    }
+    return 0;
+}
+
+int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s, int m,
+                      double tol, const sstep_options* opt, sstep_info* info) {
+    const int prec = opt ? opt->precision : SSTEP_FP64;
+    const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
+    if (!stencil_ok(A) || !f || !x || s < 1 || s > kMaxS || m < 1 || (long long)m * s > 2048 ||
+        !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
+        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0)))) {
+        if (info) std::memset(info, 0, sizeof(*info));
+        return set_status(info, SSTEP_ERR_ARG);
+    }
+    const size_t need = gmres_workspace_bytes(*A, s, m, prec);
+    const sstep_stencil Acopy = *A;
+    return run_solver(opt, need, info, [&](Ctx& c, const sstep_options& o, void* ws, size_t wsb) {
+        return gmres_solve_impl(c, Acopy, f, x, s, m, tol, o, info, ws, wsb);
+    });
+}
+
+int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, int k, double tol,
+                     const sstep_options* opt, sstep_info* info) {
+    const int prec = opt ? opt->precision : SSTEP_FP64;
+    const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
+    if (!stencil_ok(A) || !f || !x || s < 1 || s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
+        prec != SSTEP_FP64 || (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0)))) {
+        if (info) std::memset(info, 0, sizeof(*info));
+        return set_status(info, SSTEP_ERR_ARG);
+    }
+    const size_t need = omin_workspace_bytes(*A, s, k);
+    const sstep_stencil Acopy = *A;
+    return run_solver(opt, need, info, [&](Ctx& c, const sstep_options& o, void* ws, size_t wsb) {
+        return omin_solve_impl(c, Acopy, f, x, s, k, tol, o, info, ws, wsb);
+    });
+}
+
+int sstep_stencil_apply(const sstep_stencil* A, const double* x, double* y, void* stream) {
+    if (!stencil_ok(A) || !x || !y || x == y) return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        const StencilView v = make_view(*A);
+        launch_level<double>(c, v, x, nullptr, nullptr, nullptr, 1.0, 0.0, 0.0, y, nullptr, 0.0);
+        return SSTEP_OK;
+    });
+}
+
+int sstep_kernel_mpk(const sstep_stencil* A, double* Y, int64_t ldy, int s, int basis,
+                     double in_scale, double sigma, double cheb_c, double cheb_d, void* stream) {
+    if (!stencil_ok(A) || !Y || s < 1 || s > kMaxS || ldy < grid_points(*A) ||
+        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
+        !std::isfinite(in_scale) || (basis == SSTEP_BASIS_MONOMIAL && !(sigma != 0.0)) ||
+        (basis == SSTEP_BASIS_CHEBYSHEV && !(cheb_d != 0.0)))
+        return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        const StencilView v = make_view(*A);
+        // the input scale lives in device memory for the solvers; stage it
+        double* d = nullptr;
+        SSTEP_HIP(hipMallocAsync((void**)&d, sizeof(double), c.st));
+        SSTEP_HIP(hipMemcpyAsync(d, &in_scale, sizeof(double), hipMemcpyHostToDevice, c.st));
+        OpParams P{sigma, cheb_c, cheb_d};
+        launch_mpk<double>(c, v, Y, ldy, s, basis, P, d, nullptr);
+        SSTEP_HIP(hipFreeAsync(d, c.st));
+        SSTEP_HIP(hipStreamSynchronize(c.st));
+        return SSTEP_OK;
+    });
+}
+
+int sstep_kernel_gram(const double* X, int64_t ldx, int ncx, const double* Z, int64_t ldz, int ncz,
+                      int64_t N, double* G, void* stream) {
+    if (!X || !Z || !G || N < 1 || ncx < 1 || ncz < 1 || ncz > 16 || ldx < N || ldz < N ||
+        N > (1LL << 31) - 1 || ncx > 4096)
+        return SSTEP_ERR_ARG;
+    if (((uintptr_t)X & 15u) || ((uintptr_t)Z & 15u) || (ldx & 1) || (ldz & 1)) return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        double* part = nullptr;
+        const size_t np = gram_partial_doubles(N, ncx, ncz);
+        SSTEP_HIP(hipMallocAsync((void**)&part, sizeof(double) * np, c.st));
+        launch_gram<double>(c, X, ldx, ncx, Z, ldz, ncz, (const double*)nullptr, 0, 0, N, part, G,
+                            nullptr);
+        SSTEP_HIP(hipFreeAsync(part, c.st));
+        SSTEP_HIP(hipStreamSynchronize(c.st));
+        return SSTEP_OK;
+    });
+}
+
+int sstep_kernel_update(const double* X, int64_t ldx, int ncx, double* Y, int64_t ldy, int ncy,
+                        const double* M, int64_t N, void* stream) {
+    if ((ncx > 0 && (!X || !M || ldx < N)) || !Y || N < 1 || ncx < 0 || ncy < 1 || ncy > 16 ||
+        ldy < N || N > (1LL << 31) - 1)
+        return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        launch_update<double, double, double, double, false>(c, N, Y, ldy, X, ldx, ncx, nullptr, M,
+                                                             Y, ldy, ncy, nullptr, nullptr, 0.0);
+        return SSTEP_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,566 @@
+// gmres.hip -- restarted s-step GMRES(m) (Sec. 4: Alg. 4.1 s-step Arnoldi,
+// eqs. (4)-(8) least squares, Alg. 4.2 restarts) on one GPU.
+//
+// Storage.  The basis holds m*s+1 columns (FP64, or FP32 in mixed precision).
+// Column k*s is the start of block k as produced (unnormalised: the residual
+// r0 for block 0, the projected vector w_hat for later blocks); its norm
+// nu_k is kept in device state and 1/nu_k is applied when the column is read
+// by the matrix-powers kernel and folded into the coefficients of every other
+// consumer.  The matrix-powers kernel writes y_1..y_s into columns
+// k*s+1..k*s+s, which are then projected in place; column k*s+s ends up as the
+// start of block k+1.  Nothing is copied.
+//
+// Per block k (all on the device; the host only enqueues):
+//   MPK        y_j = A y_{j-1} / sigma (or Chebyshev), y_0 = w_k
+//   Gram       C = [Vbar_1..Vbar_{k-1}]^T [y_1..y_s]
+//   scalar     T_i = W_i^{-1} C_i                    (Scalar2)
+//   update     y_j -= sum_i Vbar_i T_i[:, j]          (one pass, in place)
+//   Gram       [w_k, y_1..y_s]^T [w_k, y_1..y_s]      (W_k, Vbar_k^T Yhat_s)
+//   scalar     factor W_k, g = W_k^{-1} Vbar_k^T Yhat_s   (Scalar1)
+//   update     w_hat = Yhat_s - Vbar_k g, nu_k^2 = ||w_hat||^2
+//   scalar     Hessenberg block column, L scaling, Givens, residual estimate
+// A done flag in device state makes the remaining launches of a cycle return
+// at once after the least-squares residual reaches the tolerance or the
+// Krylov space breaks down; the host synchronises once per cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dense.hpp"
+#include "launch.hpp"
+#include "solvers.hpp"
+
+namespace sstep {
+
+constexpr int kMaxBlocks = 2048;
+
+struct GmState {
+    // parameters
+    int s, m, K, ldg, basis, mixed;
+    double sigma, cc, cd;
+    double tol_rel, fnorm, tol_abs, inner_rel, rank_tol, lucky_tol;
+    double Bc[(kMaxS + 1) * kMaxS];
+    // cycle state
+    double beta, est, stop_abs, yhat2, nu_cur;
+    int kb, ncols, done, skip_n4b, skip_asm, active, conv, err, blocks_total, cycles, lucky;
+    double g[kMaxS], coefN4b[kMaxS];
+    double nu[kMaxBlocks + 1], inv_nu[kMaxBlocks + 1];
+};
+
+struct GmArrays {
+    GmState* st;
+    double* G;       // Hessenberg Gbar, (K+1) x K column-major
+    double* R;       // Givens-rotated L Gbar
+    double* cs;
+    double* sn;
+    double* rhs;     // rotated beta e_1
+    double* y;
+    double* T;       // projection coefficients of the current block, [K][s+1]
+    double* coefM;   // update coefficients, [K][s]
+    double* coefA;   // assembly coefficients, [K]
+    double* Gout;    // Gram output
+    GramFactor* Wf;  // factors of W_1..W_m
+};
+
+// ---------------------------------------------------------------------------
+// scalar kernels (one workgroup)
+// ---------------------------------------------------------------------------
+
+// ||f||^2 partials -> fnorm, absolute tolerance
+__global__ __launch_bounds__(kThreads) void k_gm_init(GmArrays a, const double* __restrict__ part,
+                                                      int npart) {
+    __shared__ double lds[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
+    double v[1] = {acc}, o[1];
+    block_sum<1>(v, lds, o);
+    if (threadIdx.x == 0) {
+        GmState* st = a.st;
+        st->fnorm = sqrt(o[0]);
+        st->tol_abs = st->tol_rel * st->fnorm;
+        st->blocks_total = 0;
+        st->cycles = 0;
+        st->conv = 0;
+        st->err = 0;
+    }
+}
+
+// Start of a cycle (Alg. 4.2 step 1): beta = ||r0|| from the residual
+// partials; converged if beta <= tol ||f||.
+__global__ __launch_bounds__(kThreads) void k_gm_cycle_start(GmArrays a,
+                                                             const double* __restrict__ part,
+                                                             int npart) {
+    __shared__ double lds[4];
+    __shared__ int go;
+    GmState* st = a.st;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
+    double v[1] = {acc}, o[1];
+    block_sum<1>(v, lds, o);
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(o[0]);
+        st->beta = beta;
+        st->kb = 0;
+        st->ncols = 0;
+        st->lucky = 0;
+        st->skip_n4b = 1;
+        st->skip_asm = 1;
+        go = 0;
+        if (!isfinite(beta)) {
+            st->err = SSTEP_ERR_NONFINITE;
+            st->done = 1;
+            st->active = 0;
+        } else if (beta <= st->tol_abs) {
+            st->conv = 1;
+            st->done = 1;
+            st->active = 0;
+        } else {
+            st->done = 0;
+            st->skip_n4b = 0;
+            st->skip_asm = 0;
+            st->active = 1;
+            st->cycles += 1;
+            st->est = beta;
+            st->nu[0] = beta;
+            st->inv_nu[0] = 1.0 / beta;
+            st->stop_abs = st->mixed ? fmax(st->tol_abs, st->inner_rel * beta) : st->tol_abs;
+            go = 1;
+        }
+    }
+    __syncthreads();
+    if (go) {
+        for (int i = threadIdx.x; i <= st->K; i += kThreads) a.rhs[i] = (i == 0) ? st->beta : 0.0;
+    }
+}
+
+// Scalar2 (Sec. 4): T_i = W_i^{-1} C_i for every previous block i, from the
+// Gram of the stored basis against y_1..y_s.  Stored column 0 of block i is
+// nu_i times the normalised w_i, hence the row scaling by 1/nu_i.
+__global__ __launch_bounds__(kThreads) void k_gm_proj(GmArrays a) {
+    GmState* st = a.st;
+    if (st->done) return;
+    const int s = st->s, kb = st->kb;
+    for (int idx = threadIdx.x; idx < kb * s; idx += kThreads) {
+        const int i = idx / s, l = idx % s + 1;  // block i, Y column l
+        double c[kMaxS];
+        for (int q = 0; q < s; ++q) {
+            const double sc = q == 0 ? st->inv_nu[i] : 1.0;
+            c[q] = a.Gout[(i * s + q) * s + (l - 1)] * sc;
+        }
+        gram_solve(a.Wf[i], c, c);
+        for (int q = 0; q < s; ++q) {
+            const double sc = q == 0 ? st->inv_nu[i] : 1.0;
+            a.T[(i * s + q) * (s + 1) + l] = c[q];
+            a.coefM[(i * s + q) * s + (l - 1)] = -c[q] * sc;
+            if (l == 1) a.T[(i * s + q) * (s + 1)] = 0.0;
+        }
+    }
+}
+
+// Scalar1 (Sec. 4): factor W_k = Vbar_k^T Vbar_k, g = W_k^{-1} Vbar_k^T Yhat_s.
+// Gb is the Gram of the stored columns [w_hat_k, y_1..y_s] (s+1 square).
+// A rank-deficient W_k (pivot below rank_tol) truncates the block to its
+// leading q columns; column q then plays the role of Yhat_s with nu = 0.
+__global__ void k_gm_block(GmArrays a) {
+    GmState* st = a.st;
+    if (st->done || threadIdx.x != 0) return;
+    const int s = st->s, kb = st->kb, s1 = s + 1;
+    const double d0 = st->inv_nu[kb];
+    double W[kMaxS * kMaxS];
+    for (int q = 0; q < s; ++q)
+        for (int p = 0; p < s; ++p)
+            W[p + q * kMaxS] = a.Gout[p * s1 + q] * (p == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
+    st->yhat2 = a.Gout[s * s1 + s];
+    GramFactor* F = &a.Wf[kb];
+    gram_factor(W, kMaxS, s, st->rank_tol, F);
+    const int q = F->rank;
+    if (q == s) {
+        double h[kMaxS];
+        for (int p = 0; p < s; ++p) h[p] = a.Gout[p * s1 + s] * (p == 0 ? d0 : 1.0);
+        gram_solve(*F, h, st->g);
+        for (int p = 0; p < s; ++p) st->coefN4b[p] = -st->g[p] * (p == 0 ? d0 : 1.0);
+        st->skip_n4b = 0;
+    } else if (q > 0) {
+        double h[kMaxS];
+        for (int p = 0; p < q; ++p) h[p] = W[p + q * kMaxS];
+        gram_solve_leading(*F, q, h, st->g);
+        st->skip_n4b = 1;
+    } else {
+        st->err = SSTEP_ERR_NONFINITE;
+        st->done = 1;
+        st->skip_n4b = 1;
+    }
+}
+
+// Hessenberg block column (eq. (5)), L scaling with D = L^T L (eq. (7)),
+// Givens QR and the least-squares residual estimate.  In coordinates of
+// U = [Vbar_1 .. Vbar_k, w_{k+1}]:  Y = U Z_k with
+//   Z_k = [T_1; ..; T_{k-1}; [I | g]; nu e^T],
+//   Gbar[:, block k] = Z_k B - sum_{i<k} Gbar[:, block i] T_i[:, 0:s].
+__global__ __launch_bounds__(kThreads) void k_gm_hess(GmArrays a, const double* __restrict__ part,
+                                                      int npart) {
+    __shared__ double lds[4];
+    __shared__ double nu_sh;
+    GmState* st = a.st;
+    if (st->done) return;
+    const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
+    const int q = a.Wf[kb].rank;
+    if (q == s) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
+        double v[1] = {acc}, o[1];
+        block_sum<1>(v, lds, o);
+        if (threadIdx.x == 0) nu_sh = sqrt(o[0]);
+    } else if (threadIdx.x == 0) {
+        nu_sh = 0.0;
+    }
+    __syncthreads();
+    const double nu = nu_sh;
+    const double* Bc = st->Bc;
+    // Hessenberg columns c0 .. c0+q-1, rows 0 .. c0+q
+    for (int idx = threadIdx.x; idx < q * (c0 + q + 1); idx += kThreads) {
+        const int j = idx / (c0 + q + 1), r = idx % (c0 + q + 1);
+        double val = 0.0;
+        for (int l = 0; l <= q; ++l) {
+            const double bl = Bc[l + j * (s + 1)];
+            if (bl == 0.0) continue;
+            double z;
+            if (r < c0) z = a.T[r * (s + 1) + l];
+            else if (r < c0 + q) z = (l < q) ? (r - c0 == l ? 1.0 : 0.0) : st->g[r - c0];
+            else z = (l == q) ? nu : 0.0;
+            val += bl * z;
+        }
+        if (r <= c0) {
+            for (int cp = (r > 0 ? r - 1 : 0); cp < c0; ++cp) {
+                const double t = a.T[cp * (s + 1) + j];
+                if (t != 0.0) val -= a.G[r + (long long)cp * ldg] * t;
+            }
+        }
+        a.G[r + (long long)(c0 + j) * ldg] = val;
+    }
+    __syncthreads();
+    // L scaling of the new columns
+    for (int idx = threadIdx.x; idx < q * (c0 + q + 1); idx += kThreads) {
+        const int j = idx / (c0 + q + 1), r = idx % (c0 + q + 1);
+        const double* gc = a.G + (long long)(c0 + j) * ldg;
+        double val;
+        if (r == c0 + q) {
+            val = gc[r];
+        } else {
+            const int i = r / s, p = r % s;
+            const int qi = (i < kb) ? s : q;
+            const GramFactor& F = a.Wf[i];
+            val = 0.0;
+            for (int b = p; b < qi; ++b) val += gram_L(F, p, b) * gc[i * s + b];
+        }
+        a.R[r + (long long)(c0 + j) * ldg] = val;
+    }
+    __syncthreads();
+    // rotations of earlier columns, one thread per new column
+    if ((int)threadIdx.x < q) {
+        double* rc = a.R + (long long)(c0 + threadIdx.x) * ldg;
+        for (int i = 0; i < c0; ++i) {
+            const double x0 = rc[i], x1 = rc[i + 1];
+            rc[i] = a.cs[i] * x0 + a.sn[i] * x1;
+            rc[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < q; ++j) {
+            double* rc = a.R + (long long)(c0 + j) * ldg;
+            for (int i = c0; i < c0 + j; ++i) {
+                const double x0 = rc[i], x1 = rc[i + 1];
+                rc[i] = a.cs[i] * x0 + a.sn[i] * x1;
+                rc[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
+            }
+            const int cj = c0 + j;
+            const double x0 = rc[cj], x1 = rc[cj + 1];
+            double cth = 1.0, sth = 0.0;
+            if (x1 != 0.0) {
+                const double h = hypot(x0, x1);
+                cth = x0 / h;
+                sth = x1 / h;
+            }
+            a.cs[cj] = cth;
+            a.sn[cj] = sth;
+            rc[cj] = cth * x0 + sth * x1;
+            rc[cj + 1] = 0.0;
+            const double g0 = a.rhs[cj];
+            a.rhs[cj + 1] = -sth * g0;
+            a.rhs[cj] = cth * g0;
+        }
+        const double est = fabs(a.rhs[c0 + q]);
+        st->est = est;
+        st->ncols = c0 + q;
+        st->kb = kb + 1;
+        st->blocks_total += 1;
+        st->nu[kb + 1] = nu;
+        st->inv_nu[kb + 1] = nu > 0.0 ? 1.0 / nu : 0.0;
+        const bool lucky = (q == s) && !(nu > st->lucky_tol * sqrt(st->yhat2));
+        if (!isfinite(est)) {
+            st->err = SSTEP_ERR_NONFINITE;
+            st->done = 1;
+        } else if (est <= st->stop_abs || lucky || q < s || kb + 1 == st->m) {
+            st->done = 1;
+        }
+        if (st->done) st->skip_n4b = 1;
+        st->lucky = lucky;
+    }
+}
+
+// Least-squares solution y = R^{-1} rhs (eq. (8)) and assembly coefficients.
+__global__ __launch_bounds__(kThreads) void k_gm_solve(GmArrays a) {
+    __shared__ double b[2048];
+    __shared__ double yi;
+    GmState* st = a.st;
+    if (!st->active) return;
+    const int n = st->ncols, s = st->s, ldg = st->ldg;
+    for (int i = threadIdx.x; i < n; i += kThreads) b[i] = a.rhs[i];
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {
+        if (threadIdx.x == 0) {
+            yi = b[i] / a.R[i + (long long)i * ldg];
+            a.y[i] = yi;
+        }
+        __syncthreads();
+        const double v = yi;
+        for (int r = threadIdx.x; r < i; r += kThreads) b[r] -= a.R[r + (long long)i * ldg] * v;
+        __syncthreads();
+    }
+    for (int c = threadIdx.x; c < n; c += kThreads)
+        a.coefA[c] = a.y[c] * ((c % s == 0) ? st->inv_nu[c / s] : 1.0);
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+struct GmLayout {
+    long long N, ld;
+    int s, m, K;
+    size_t off_basis, off_state, off_G, off_R, off_cs, off_sn, off_rhs, off_y, off_T, off_coefM,
+        off_coefA, off_Gout, off_Wf, off_gpart, off_npart, off_rpart, off_scratch, total;
+};
+
+static GmLayout gm_layout(const sstep_stencil& A, int s, int m, int precision) {
+    GmLayout L{};
+    L.N = grid_points(A);
+    L.ld = col_stride(L.N);
+    L.s = s;
+    L.m = m;
+    L.K = m * s;
+    const size_t esz = precision == SSTEP_MIXED ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const int K = L.K;
+    L.off_basis = take((size_t)(K + 1) * L.ld * esz);
+    L.off_state = take(sizeof(GmState));
+    L.off_G = take(sizeof(double) * (size_t)(K + 1) * K);
+    L.off_R = take(sizeof(double) * (size_t)(K + 1) * K);
+    L.off_cs = take(sizeof(double) * (K + 1));
+    L.off_sn = take(sizeof(double) * (K + 1));
+    L.off_rhs = take(sizeof(double) * (K + 1));
+    L.off_y = take(sizeof(double) * (K + 1));
+    L.off_T = take(sizeof(double) * (size_t)K * (s + 1));
+    L.off_coefM = take(sizeof(double) * (size_t)K * s);
+    L.off_coefA = take(sizeof(double) * (K + 1));
+    L.off_Gout = take(sizeof(double) * (size_t)(K + 1) * (s + 1));
+    L.off_Wf = take(sizeof(GramFactor) * (size_t)m);
+    size_t gp = gram_partial_doubles(L.N, s + 1, s + 1);
+    for (int ncx = s; ncx < K; ncx += s) gp = std::max(gp, gram_partial_doubles(L.N, ncx, s));
+    L.off_gpart = take(sizeof(double) * gp);
+    L.off_npart = take(sizeof(double) * (size_t)update_blocks(L.N));
+    const StencilView v = make_view(A);
+    L.off_rpart = take(sizeof(double) * (size_t)stencil_blocks(v));
+    L.off_scratch = take(sizeof(double) * 64 * 3);
+    L.total = off;
+    return L;
+}
+
+size_t gmres_workspace_bytes(const sstep_stencil& A, int s, int m, int precision) {
+    return gm_layout(A, s, m, precision).total;
+}
+
+template <typename T>
+static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* x, int s, int m,
+                     double tol, const sstep_options& opt, sstep_info* info, char* ws,
+                     const GmLayout& L) {
+    const StencilView v = make_view(Ast);
+    const long long N = L.N, ld = L.ld;
+    const int K = L.K;
+    T* basis = reinterpret_cast<T*>(ws + L.off_basis);
+    GmArrays a;
+    a.st = reinterpret_cast<GmState*>(ws + L.off_state);
+    a.G = reinterpret_cast<double*>(ws + L.off_G);
+    a.R = reinterpret_cast<double*>(ws + L.off_R);
+    a.cs = reinterpret_cast<double*>(ws + L.off_cs);
+    a.sn = reinterpret_cast<double*>(ws + L.off_sn);
+    a.rhs = reinterpret_cast<double*>(ws + L.off_rhs);
+    a.y = reinterpret_cast<double*>(ws + L.off_y);
+    a.T = reinterpret_cast<double*>(ws + L.off_T);
+    a.coefM = reinterpret_cast<double*>(ws + L.off_coefM);
+    a.coefA = reinterpret_cast<double*>(ws + L.off_coefA);
+    a.Gout = reinterpret_cast<double*>(ws + L.off_Gout);
+    a.Wf = reinterpret_cast<GramFactor*>(ws + L.off_Wf);
+    double* gpart = reinterpret_cast<double*>(ws + L.off_gpart);
+    double* npart = reinterpret_cast<double*>(ws + L.off_npart);
+    double* rpart = reinterpret_cast<double*>(ws + L.off_rpart);
+    double* scratch = reinterpret_cast<double*>(ws + L.off_scratch);
+    GmState* dst = a.st;
+
+    const OpParams P = op_params(Ast, opt.sigma, c.st, scratch);
+    // host-initialised parameters
+    GmState h;
+    std::memset(&h, 0, sizeof(h));
+    h.s = s;
+    h.m = m;
+    h.K = K;
+    h.ldg = K + 1;
+    h.basis = opt.basis;
+    h.mixed = (opt.precision == SSTEP_MIXED);
+    h.sigma = P.sigma;
+    h.cc = P.cc;
+    h.cd = P.cd;
+    h.tol_rel = tol;
+    h.inner_rel = opt.inner_tol > 0.0 ? opt.inner_tol : 1e-5;
+    h.rank_tol = 1e-14;
+    h.lucky_tol = 1e-14;
+    h.done = 1;
+    basis_matrix(s, opt.basis, P, h.Bc);
+    SSTEP_HIP(hipMemcpyAsync(dst, &h, sizeof(GmState), hipMemcpyHostToDevice, c.st));
+
+    const int max_blocks = opt.max_iters > 0 ? opt.max_iters : 10000;
+    const double vb = (double)N * sizeof(T);
+
+    // ||f||
+    {
+        c.cur_block = -1;
+        launch_update<double, double, T, double, true>(c, N, f, 0, (const double*)nullptr, 0, 0,
+                                                       nullptr, nullptr, basis, ld, 1, npart,
+                                                       nullptr, 8.0 * N + vb, SSTEP_K_SCALAR);
+        c.begin(SSTEP_K_SCALAR, 0.0);
+        hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kThreads), 0, c.st, a, npart,
+                           (int)update_blocks(N));
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+    }
+    const int nrpart = (int)stencil_blocks(v);
+    const int nnpart = (int)update_blocks(N);
+    auto residual_and_start = [&]() {
+        c.cur_block = -1;
+        launch_residual<T>(c, v, f, x, basis, rpart);
+        c.begin(SSTEP_K_SCALAR, 0.0);
+        hipLaunchKernelGGL(k_gm_cycle_start, dim3(1), dim3(kThreads), 0, c.st, a, rpart, nrpart);
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+    };
+    struct Ret {
+        int conv, err, blocks_total, cycles, ncols, kb;
+        double est, beta, fnorm, tol_abs;
+    } ret{};
+    auto read_state = [&]() {
+        GmState hs;
+        SSTEP_HIP(hipMemcpyAsync(&hs, dst, sizeof(GmState), hipMemcpyDeviceToHost, c.st));
+        SSTEP_HIP(hipStreamSynchronize(c.st));
+        ret.conv = hs.conv;
+        ret.err = hs.err;
+        ret.blocks_total = hs.blocks_total;
+        ret.cycles = hs.cycles;
+        ret.ncols = hs.ncols;
+        ret.kb = hs.kb;
+        ret.est = hs.est;
+        ret.beta = hs.beta;
+        ret.fnorm = hs.fnorm;
+        ret.tol_abs = hs.tol_abs;
+    };
+
+    residual_and_start();
+    read_state();
+    c.harvest(0);
+    int matvecs = 1, cycles = 0;
+    int status = SSTEP_NOT_CONVERGED;
+    double last_est = ret.beta;
+    for (;;) {
+        if (ret.err) { status = ret.err; break; }
+        if (ret.conv) { status = SSTEP_OK; break; }
+        const int nb = std::min(m, max_blocks - ret.blocks_total);
+        if (nb <= 0) { status = SSTEP_NOT_CONVERGED; break; }
+        ++cycles;
+        const int* done = &dst->done;
+        for (int kb = 0; kb < nb; ++kb) {
+            c.cur_block = kb;
+            T* Yk = basis + (long long)kb * s * ld;
+            launch_mpk<T>(c, v, Yk, ld, s, opt.basis, P, &dst->inv_nu[kb], done);
+            if (kb > 0) {
+                const int ncx = kb * s;
+                launch_gram<T>(c, basis, ld, ncx, Yk + ld, ld, s, (const T*)nullptr, 0, 0, N, gpart,
+                               a.Gout, done);
+                c.begin(SSTEP_K_SCALAR, 0.0);
+                hipLaunchKernelGGL(k_gm_proj, dim3(1), dim3(kThreads), 0, c.st, a);
+                SSTEP_HIP(hipGetLastError());
+                c.end();
+                launch_update<T, T, T, T, false>(c, N, Yk + ld, ld, basis, ld, ncx, nullptr,
+                                                 a.coefM, Yk + ld, ld, s, nullptr, done,
+                                                 vb * (ncx + 2 * s));
+            }
+            launch_gram<T>(c, Yk, ld, s + 1, Yk, ld, s + 1, (const T*)nullptr, 0, 0, N, gpart,
+                           a.Gout, done);
+            c.begin(SSTEP_K_SCALAR, 0.0);
+            hipLaunchKernelGGL(k_gm_block, dim3(1), dim3(64), 0, c.st, a);
+            SSTEP_HIP(hipGetLastError());
+            c.end();
+            launch_update<T, T, T, T, true>(c, N, Yk + (long long)s * ld, ld, Yk, ld, s, nullptr,
+                                            dst->coefN4b, Yk + (long long)s * ld, ld, 1, npart,
+                                            &dst->skip_n4b, vb * (s + 2));
+            c.begin(SSTEP_K_SCALAR, 0.0);
+            hipLaunchKernelGGL(k_gm_hess, dim3(1), dim3(kThreads), 0, c.st, a, npart, nnpart);
+            SSTEP_HIP(hipGetLastError());
+            c.end();
+        }
+        c.cur_block = -1;
+        c.begin(SSTEP_K_SCALAR, 0.0);
+        hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(kThreads), 0, c.st, a);
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+        // x = x0 + V y (eq. (8)); column count read on the device
+        launch_update<T, double, double, double, false>(c, N, x, 0, basis, ld, K, &dst->ncols,
+                                                        a.coefA, x, 0, 1, nullptr, &dst->skip_asm,
+                                                        0.0);
+        residual_and_start();
+        const int before = ret.blocks_total;
+        read_state();
+        const int ran = ret.blocks_total - before;
+        matvecs += ran * s + 1;
+        c.harvest(ran);
+        last_est = ret.est;
+    }
+    if (info) {
+        info->iters = ret.blocks_total;
+        info->cycles = cycles;
+        info->matvecs = matvecs;
+        info->rel_resid = ret.fnorm > 0 ? ret.beta / ret.fnorm : ret.beta;
+        info->rel_resid_est = ret.fnorm > 0 ? last_est / ret.fnorm : last_est;
+        info->sigma = P.sigma;
+        info->cheb_centre = P.cc;
+        info->cheb_half_width = P.cd;
+    }
+    return status;
+}
+
+int gmres_solve_impl(Ctx& c, const sstep_stencil& A, const double* f, double* x, int s, int m,
+                     double tol, const sstep_options& opt, sstep_info* info, void* ws,
+                     size_t ws_bytes) {
+    const GmLayout L = gm_layout(A, s, m, opt.precision);
+    if (ws_bytes < L.total) return SSTEP_ERR_NOMEM;
+    if (opt.precision == SSTEP_MIXED)
+        return gmres_run<float>(c, A, f, x, s, m, tol, opt, info, (char*)ws, L);
+    return gmres_run<double>(c, A, f, x, s, m, tol, opt, info, (char*)ws, L);
+}
+
+}  // namespace sstep

@@ -1,0 +1,341 @@
+// kernels.hpp -- HIP kernels (gfx950) for the data-parallel part of the
+// s-step methods: stencil operator, matrix powers, true residual, block Gram
+// (all inner products of one s-step), block updates (linear combinations).
+//
+// Memory layout: every vector is one column of N elements; a block of
+// columns has a column stride ld (a multiple of 64 elements, so each column
+// starts 256-byte aligned).  Reductions are deterministic: per-workgroup
+// partial sums in a fixed order, then a fixed-order second pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sstep {
+
+constexpr int kThreads = 256;  // 4 wave64 per workgroup
+
+struct StencilView {
+    int ndim, nx, ny, nz;
+    long long N;
+    double c[7];
+    const double* coef;  // [7][N] or nullptr
+};
+
+// Workgroup b is dispatched to XCD (b mod 8).  Give every XCD a contiguous
+// range of logical tiles so that neighbouring tiles (stencil halos, the
+// shared right-hand block of a Gram) meet in the same L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+    const unsigned nfull = nb & ~7u;
+    if (b >= nfull) return b;
+    return (b & 7u) * (nfull >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NV per-thread values over the workgroup.  Result valid in out[0..NV)
+// for threads 0..NV-1 (written by those threads only).  lds: >= 4*NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(const double (&v)[NV], double* lds, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = wave_sum(v[k]);
+        if (lane == 0) lds[wave * NV + k] = t;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NV; k += kThreads)
+        out[k] = (lds[k] + lds[NV + k]) + (lds[2 * NV + k] + lds[3 * NV + k]);
+}
+
+template <typename T>
+__device__ __forceinline__ double to_f64(T v) { return static_cast<double>(v); }
+
+// ---------------------------------------------------------------------------
+// Stencil level: out = alpha * A(y) + beta * y + gam * z,
+//   y = in * in_scale, z = prev * prev_scale  (scales from device pointers,
+//   nullptr = 1).  One workgroup per 256-point row segment; rows are mapped
+//   XCD-contiguously.  Neighbour order -x, +x, -y, +y, -z, +z, then centre.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_stencil_level(
+    StencilView A, int nseg, const T* __restrict__ in, const double* __restrict__ in_scale,
+    const T* __restrict__ prev, const double* __restrict__ prev_scale, double alpha, double beta,
+    double gam, T* __restrict__ out, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int seg = t % nseg;
+    const unsigned row = t / nseg;
+    const int j = row % A.ny, l = row / A.ny;
+    const int i = seg * kThreads + threadIdx.x;
+    if (i >= A.nx) return;
+    const long long sy = A.nx, sz = (long long)A.nx * A.ny;
+    const long long p = i + sy * j + sz * l;
+    T c[7];
+    if (A.coef) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) c[q] = (q < 2 * A.ndim + 1) ? (T)A.coef[q * A.N + p] : T(0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) c[q] = (T)A.c[q];
+    }
+    T acc = 0;
+    if (i > 0) acc += c[1] * in[p - 1];
+    if (i < A.nx - 1) acc += c[2] * in[p + 1];
+    if (j > 0) acc += c[3] * in[p - sy];
+    if (j < A.ny - 1) acc += c[4] * in[p + sy];
+    if (A.ndim == 3) {
+        if (l > 0) acc += c[5] * in[p - sz];
+        if (l < A.nz - 1) acc += c[6] * in[p + sz];
+    }
+    const T xc = in[p];
+    acc += c[0] * xc;
+    const T si = in_scale ? (T)*in_scale : T(1);
+    T r = (T)alpha * si * acc;
+    if (beta != 0.0) r += (T)beta * si * xc;
+    if (gam != 0.0) {
+        const T sp = prev_scale ? (T)*prev_scale : T(1);
+        r += (T)gam * sp * prev[p];
+    }
+    out[p] = r;
+}
+
+// ---------------------------------------------------------------------------
+// True residual r = f - A x in FP64 (x, f FP64); r stored as TR; per
+// workgroup partial sum of r^2 (FP64, before rounding to TR).
+// ---------------------------------------------------------------------------
+template <typename TR>
+__global__ __launch_bounds__(kThreads) void k_residual(StencilView A, int nseg,
+                                                       const double* __restrict__ f,
+                                                       const double* __restrict__ x,
+                                                       TR* __restrict__ r, double* __restrict__ part) {
+    __shared__ double lds[4];
+    const unsigned t = xcd_remap(blockIdx.x, gridDim.x);
+    const int seg = t % nseg;
+    const unsigned row = t / nseg;
+    const int j = row % A.ny, l = row / A.ny;
+    const int i = seg * kThreads + threadIdx.x;
+    double rr = 0.0;
+    if (i < A.nx) {
+        const long long sy = A.nx, sz = (long long)A.nx * A.ny;
+        const long long p = i + sy * j + sz * l;
+        double c[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            c[q] = A.coef ? ((q < 2 * A.ndim + 1) ? A.coef[q * A.N + p] : 0.0) : A.c[q];
+        double acc = 0.0;
+        if (i > 0) acc += c[1] * x[p - 1];
+        if (i < A.nx - 1) acc += c[2] * x[p + 1];
+        if (j > 0) acc += c[3] * x[p - sy];
+        if (j < A.ny - 1) acc += c[4] * x[p + sy];
+        if (A.ndim == 3) {
+            if (l > 0) acc += c[5] * x[p - sz];
+            if (l < A.nz - 1) acc += c[6] * x[p + sz];
+        }
+        acc += c[0] * x[p];
+        const double v = f[p] - acc;
+        r[p] = (TR)v;
+        rr = v * v;
+    }
+    double v1[1] = {rr}, o[1];
+    block_sum<1>(v1, lds, o);
+    if (threadIdx.x == 0) part[t] = o[0];
+}
+
+// ---------------------------------------------------------------------------
+// Block Gram, stage 1: for a point chunk and a tile of CA columns of X,
+//   partial[chunk][c][j] = sum_{p in chunk} X[c][p] * Z[j][p],  j < KZ
+// Z = [Z1 (nz1 columns) | Z2 (nz2 columns)], nz1 + nz2 <= KZ.  Accumulation
+// in FP64.  Workgroups of one chunk are consecutive on one XCD, so Z is read
+// from HBM once and then served by that XCD's L2.
+// ---------------------------------------------------------------------------
+template <typename T, int CA, int KZ>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(
+    const T* __restrict__ X, long long ldx, int ncx, const T* __restrict__ Z1, long long ldz1,
+    int nz1, const T* __restrict__ Z2, long long ldz2, int nz2, long long N, long long chunk,
+    int nct, double* __restrict__ part, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double lds[4 * CA * KZ];
+    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = b % nct;
+    const long long ch = b / nct;
+    const long long p0 = ch * chunk;
+    const long long p1 = (p0 + chunk < N) ? p0 + chunk : N;
+    const int c0 = ct * CA;
+    const int nz = nz1 + nz2;
+    double acc[CA][KZ];
+#pragma unroll
+    for (int a = 0; a < CA; ++a)
+#pragma unroll
+        for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = 0.0;
+
+    const T* zc[KZ];
+#pragma unroll
+    for (int jz = 0; jz < KZ; ++jz)
+        zc[jz] = jz < nz1 ? Z1 + jz * ldz1 : (jz < nz ? Z2 + (jz - nz1) * ldz2 : Z1);
+    const T* xc[CA];
+#pragma unroll
+    for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : c0) * ldx;
+
+    // two consecutive points per thread per step (16-byte loads for FP64)
+    for (long long p = p0 + 2 * threadIdx.x; p < p1; p += 2 * kThreads) {
+        if (p + 1 < p1) {
+            double z0[KZ], z1[KZ];
+#pragma unroll
+            for (int jz = 0; jz < KZ; ++jz) {
+                if (jz < nz) {
+                    if constexpr (sizeof(T) == 8) {
+                        const double2 v = *reinterpret_cast<const double2*>(zc[jz] + p);
+                        z0[jz] = v.x; z1[jz] = v.y;
+                    } else {
+                        const float2 v = *reinterpret_cast<const float2*>(zc[jz] + p);
+                        z0[jz] = v.x; z1[jz] = v.y;
+                    }
+                } else {
+                    z0[jz] = 0.0; z1[jz] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < CA; ++a) {
+                if (c0 + a < ncx) {
+                    double x0, x1;
+                    if constexpr (sizeof(T) == 8) {
+                        const double2 v = *reinterpret_cast<const double2*>(xc[a] + p);
+                        x0 = v.x; x1 = v.y;
+                    } else {
+                        const float2 v = *reinterpret_cast<const float2*>(xc[a] + p);
+                        x0 = v.x; x1 = v.y;
+                    }
+#pragma unroll
+                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], fma(x1, z1[jz], acc[a][jz]));
+                }
+            }
+        } else {
+            double z0[KZ];
+#pragma unroll
+            for (int jz = 0; jz < KZ; ++jz) z0[jz] = jz < nz ? to_f64(zc[jz][p]) : 0.0;
+#pragma unroll
+            for (int a = 0; a < CA; ++a) {
+                if (c0 + a < ncx) {
+                    const double x0 = to_f64(xc[a][p]);
+#pragma unroll
+                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
+                }
+            }
+        }
+    }
+    double flat[CA * KZ], outv[CA * KZ];
+#pragma unroll
+    for (int a = 0; a < CA; ++a)
+#pragma unroll
+        for (int jz = 0; jz < KZ; ++jz) flat[a * KZ + jz] = acc[a][jz];
+    block_sum<CA * KZ>(flat, lds, outv);
+    for (int k = threadIdx.x; k < CA * KZ; k += kThreads) {
+        const int a = k / KZ, jz = k % KZ;
+        if (c0 + a < ncx && jz < nz) part[(ch * ncx + c0 + a) * KZ + jz] = outv[k];
+    }
+}
+
+// Block Gram, stage 2: G[c*nz + j] = sum over chunks (fixed order).
+static __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ part,
+                                                                 int nchunk, int ncx, int KZ,
+                                                                 int nz, double* __restrict__ G,
+                                                                 const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int o = blockIdx.x * kThreads + threadIdx.x;
+    if (o >= ncx * nz) return;
+    const int c = o / nz, jz = o % nz;
+    double s = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) s += part[((long long)ch * ncx + c) * KZ + jz];
+    G[o] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Block update (tall-skinny linear combination):
+//   out[:, l] = base[:, l] + sum_{c < n2} V[:, c] * M[c * nout + l],  l < nout <= NOUT
+// base has type TB (may alias out: every thread reads all its inputs before
+// writing).  n2 may come from device memory (n2_dev) so a launch can cover a
+// column count that is only known on the device.  Arithmetic in TA.
+// NORM: per-workgroup partial sum of out[:,0]^2 (FP64) into part[blockIdx].
+// ---------------------------------------------------------------------------
+template <typename TV, typename TB, typename TO, typename TA, int NOUT, bool NORM>
+__global__ __launch_bounds__(kThreads) void k_update(
+    long long N, const TB* base, long long ldb, const TV* V, long long ldv, int n2,
+    const int* __restrict__ n2_dev, const double* __restrict__ M, TO* out, long long ldo,
+    int nout, double* __restrict__ part, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int nc = n2_dev ? *n2_dev : n2;
+    constexpr int PPT = 2;  // points per thread
+    const long long p = ((long long)blockIdx.x * kThreads + threadIdx.x) * PPT;
+    double nrm = 0.0;
+    if (p < N) {
+        const bool full = p + 1 < N;
+        TA acc[NOUT][PPT];
+#pragma unroll
+        for (int l = 0; l < NOUT; ++l) {
+            if (base && l < nout) {
+                const TB* bc = base + l * ldb;
+                acc[l][0] = (TA)bc[p];
+                acc[l][1] = full ? (TA)bc[p + 1] : TA(0);
+            } else {
+                acc[l][0] = acc[l][1] = TA(0);
+            }
+        }
+        int c = 0;
+        for (; c + 4 <= nc; c += 4) {
+            TA v[4][PPT];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const TV* vc = V + (long long)(c + u) * ldv;
+                v[u][0] = (TA)vc[p];
+                v[u][1] = full ? (TA)vc[p + 1] : TA(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int l = 0; l < NOUT; ++l) {
+                    if (l < nout) {
+                        const TA m = (TA)M[(c + u) * nout + l];
+                        acc[l][0] = fma(v[u][0], m, acc[l][0]);
+                        acc[l][1] = fma(v[u][1], m, acc[l][1]);
+                    }
+                }
+        }
+        for (; c < nc; ++c) {
+            const TV* vc = V + (long long)c * ldv;
+            const TA v0 = (TA)vc[p], v1 = full ? (TA)vc[p + 1] : TA(0);
+#pragma unroll
+            for (int l = 0; l < NOUT; ++l) {
+                if (l < nout) {
+                    const TA m = (TA)M[c * nout + l];
+                    acc[l][0] = fma(v0, m, acc[l][0]);
+                    acc[l][1] = fma(v1, m, acc[l][1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < NOUT; ++l) {
+            if (l < nout) {
+                TO* oc = out + l * ldo;
+                oc[p] = (TO)acc[l][0];
+                if (full) oc[p + 1] = (TO)acc[l][1];
+            }
+        }
+        if (NORM) {
+            const double a0 = (double)acc[0][0], a1 = full ? (double)acc[0][1] : 0.0;
+            nrm = a0 * a0 + a1 * a1;
+        }
+    }
+    if (NORM) {
+        __shared__ double lds[4];
+        double v1[1] = {nrm}, o[1];
+        block_sum<1>(v1, lds, o);
+        if (threadIdx.x == 0) part[blockIdx.x] = o[0];
+    }
+}
+
+}  // namespace sstep

@@ -1,0 +1,383 @@
+// launch.hpp -- host-side launch helpers, per-launch profiling records,
+// operator parameters (power scaling, Chebyshev interval) and workspace
+// carving shared by the solver drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sstep.h"
+#include "kernels.hpp"
+
+namespace sstep {
+
+#define SSTEP_HIP(call)                                   \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) throw HipFailure{e_, #call}; \
+    } while (0)
+
+struct HipFailure {
+    hipError_t err;
+    const char* what;
+};
+
+inline long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+inline long long grid_points(const sstep_stencil& A) {
+    return (long long)A.nx * A.ny * (A.ndim == 3 ? A.nz : 1);
+}
+
+inline StencilView make_view(const sstep_stencil& A) {
+    StencilView v;
+    v.ndim = A.ndim;
+    v.nx = A.nx;
+    v.ny = A.ny;
+    v.nz = A.ndim == 3 ? A.nz : 1;
+    v.N = grid_points(A);
+    for (int q = 0; q < 7; ++q) v.c[q] = A.c[q];
+    v.coef = A.coef;
+    return v;
+}
+
+// Column stride of basis blocks: a multiple of 64 elements (256 bytes FP32,
+// 512 bytes FP64) so every column starts aligned for 16-byte vector access.
+inline long long col_stride(long long N) { return round_up(std::max(N, 1LL), 64); }
+
+// One profiled launch: class, algorithmic bytes, the block of the restart
+// cycle it belongs to (-1: always executed), and the event index before it.
+struct LaunchRec {
+    int cls;
+    double bytes;
+    int block;
+    int ev;
+};
+
+struct Ctx {
+    hipStream_t st = nullptr;
+    bool profile = false;
+    std::vector<hipEvent_t> pool;
+    int nev = 0;
+    std::vector<LaunchRec> recs;
+    int cur_block = -1;
+    // totals
+    long long launches[SSTEP_K_NCLASS] = {0};
+    double ms[SSTEP_K_NCLASS] = {0};
+    double bytes[SSTEP_K_NCLASS] = {0};
+
+    ~Ctx() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+    hipEvent_t next_event() {
+        if (nev == (int)pool.size()) {
+            hipEvent_t e;
+            SSTEP_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[nev++];
+    }
+    // call before a kernel launch
+    void begin(int cls, double bytes_) {
+        if (!profile) return;
+        if (recs.empty() || recs.back().ev + 1 != nev) {
+            SSTEP_HIP(hipEventRecord(next_event(), st));
+        }
+        recs.push_back({cls, bytes_, cur_block, nev - 1});
+    }
+    // call after a kernel launch
+    void end() {
+        if (!profile) return;
+        SSTEP_HIP(hipEventRecord(next_event(), st));
+    }
+    // after a stream synchronize: fold records of executed blocks into totals
+    // (blocks_done: blocks of the cycle that ran; launches of later blocks
+    // exited at their first instruction and are not counted).
+    void harvest(int blocks_done) {
+        if (!profile) return;
+        for (const auto& r : recs) {
+            if (r.block >= 0 && r.block >= blocks_done) continue;
+            float t = 0.f;
+            SSTEP_HIP(hipEventElapsedTime(&t, pool[r.ev], pool[r.ev + 1]));
+            launches[r.cls] += 1;
+            ms[r.cls] += t;
+            bytes[r.cls] += r.bytes;
+        }
+        recs.clear();
+        nev = 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// operator-derived parameters (host side)
+// ---------------------------------------------------------------------------
+inline double pow2_ceil(double b) {
+    if (!(b > 0.0)) return 1.0;
+    int e;
+    const double m = std::frexp(b, &e);
+    return m == 0.5 ? std::ldexp(1.0, e - 1) : std::ldexp(1.0, e);
+}
+
+// Gershgorin row-sum maximum and Chebyshev interval from device coefficients.
+static __global__ __launch_bounds__(kThreads) void k_coef_bounds(StencilView A,
+                                                                 double* __restrict__ part) {
+    __shared__ double lds[4 * 3];
+    const int nq = 2 * A.ndim + 1;
+    double rmax = 0.0, lo = 1e300, hi = -1e300;
+    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < A.N;
+         p += (long long)gridDim.x * kThreads) {
+        double r = 0.0;
+        for (int q = 1; q < nq; ++q) r += fabs(A.coef[q * A.N + p]);
+        const double c0 = A.coef[p];
+        rmax = fmax(rmax, r + fabs(c0));
+        lo = fmin(lo, c0 - r);
+        hi = fmax(hi, c0 + r);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        rmax = fmax(rmax, __shfl_xor(rmax, off, 64));
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+        lds[wave * 3 + 0] = rmax;
+        lds[wave * 3 + 1] = lo;
+        lds[wave * 3 + 2] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = lds[0], b = lds[1], c = lds[2];
+        for (int w = 1; w < 4; ++w) {
+            a = fmax(a, lds[w * 3]);
+            b = fmin(b, lds[w * 3 + 1]);
+            c = fmax(c, lds[w * 3 + 2]);
+        }
+        part[blockIdx.x * 3 + 0] = a;
+        part[blockIdx.x * 3 + 1] = b;
+        part[blockIdx.x * 3 + 2] = c;
+    }
+}
+
+struct OpParams {
+    double sigma, cc, cd;
+};
+
+// sigma: smallest power of two >= max_p sum_q |a_pq| (exact scaling);
+// Chebyshev interval: for constant coefficients the spectrum of the symmetric
+// part (per axis cos(pi/(n+1)) times |c_- + c_+|), else a Gershgorin interval.
+inline OpParams op_params(const sstep_stencil& A, double sigma_opt, hipStream_t st,
+                          double* dev_scratch /* >= 3*64 doubles */) {
+    OpParams P{};
+    const int nd = A.ndim == 3 ? 3 : 2;
+    if (!A.coef) {
+        double b = 0.0;
+        for (int q = 0; q < 2 * nd + 1; ++q) b += std::fabs(A.c[q]);
+        P.sigma = pow2_ceil(b);
+        const int n[3] = {A.nx, A.ny, A.ndim == 3 ? A.nz : 1};
+        double hw = 0.0;
+        for (int a = 0; a < nd; ++a)
+            hw += std::fabs(A.c[1 + 2 * a] + A.c[2 + 2 * a]) * std::cos(M_PI / (n[a] + 1));
+        P.cc = A.c[0];
+        P.cd = hw;
+    } else {
+        const StencilView v = make_view(A);
+        hipLaunchKernelGGL(k_coef_bounds, dim3(64), dim3(kThreads), 0, st, v, dev_scratch);
+        SSTEP_HIP(hipGetLastError());
+        double h[64 * 3];
+        SSTEP_HIP(hipMemcpyAsync(h, dev_scratch, sizeof(h), hipMemcpyDeviceToHost, st));
+        SSTEP_HIP(hipStreamSynchronize(st));
+        double a = 0.0, lo = 1e300, hi = -1e300;
+        for (int b = 0; b < 64; ++b) {
+            a = std::max(a, h[3 * b]);
+            lo = std::min(lo, h[3 * b + 1]);
+            hi = std::max(hi, h[3 * b + 2]);
+        }
+        P.sigma = pow2_ceil(a);
+        P.cc = 0.5 * (lo + hi);
+        P.cd = 0.5 * (hi - lo);
+    }
+    if (!(P.cd > 0.0)) P.cd = std::fabs(P.cc) > 0.0 ? std::fabs(P.cc) : 1.0;
+    if (sigma_opt > 0.0) P.sigma = sigma_opt;
+    return P;
+}
+
+// Basis change B ((s+1) x s, column-major ld s+1): A Y[:, 0:s] = Y B.
+inline void basis_matrix(int s, int basis, const OpParams& P, double* B) {
+    std::memset(B, 0, sizeof(double) * (s + 1) * s);
+    for (int j = 0; j < s; ++j) {
+        if (basis == SSTEP_BASIS_CHEBYSHEV) {
+            if (j == 0) {
+                B[0] = P.cc;
+                B[1] = P.cd;
+            } else {
+                B[(j - 1) + j * (s + 1)] = 0.5 * P.cd;
+                B[j + j * (s + 1)] = P.cc;
+                B[(j + 1) + j * (s + 1)] = 0.5 * P.cd;
+            }
+        } else {
+            B[(j + 1) + j * (s + 1)] = P.sigma;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+inline int stencil_segments(const StencilView& v) { return (v.nx + kThreads - 1) / kThreads; }
+inline long long stencil_blocks(const StencilView& v) {
+    return (long long)stencil_segments(v) * v.ny * v.nz;
+}
+
+template <typename T>
+inline void launch_level(Ctx& c, const StencilView& v, const T* in, const double* in_scale,
+                         const T* prev, const double* prev_scale, double alpha, double beta,
+                         double gam, T* out, const int* skip, double bytes) {
+    c.begin(SSTEP_K_MPK, bytes);
+    const int nseg = stencil_segments(v);
+    hipLaunchKernelGGL(k_stencil_level<T>, dim3((unsigned)stencil_blocks(v)), dim3(kThreads), 0,
+                       c.st, v, nseg, in, in_scale, prev, prev_scale, alpha, beta, gam, out, skip);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+// Matrix powers of column 0 of Y into columns 1..s (kernel per level).
+template <typename T>
+inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s, int basis,
+                       const OpParams& P, const double* in_scale, const int* skip) {
+    const double vb = (double)v.N * sizeof(T);
+    const double per_level = vb * (1.0 + s) / s;  // algorithmic: read 1, write s
+    for (int j = 1; j <= s; ++j) {
+        const T* yin = Y + (j - 1) * ldy;
+        const double* sc = (j == 1) ? in_scale : nullptr;
+        if (basis == SSTEP_BASIS_CHEBYSHEV) {
+            if (j == 1) {
+                launch_level<T>(c, v, yin, sc, nullptr, nullptr, 1.0 / P.cd, -P.cc / P.cd, 0.0,
+                                Y + j * ldy, skip, per_level);
+            } else {
+                const double* psc = (j == 2) ? in_scale : nullptr;
+                launch_level<T>(c, v, yin, nullptr, Y + (j - 2) * ldy, psc, 2.0 / P.cd,
+                                -2.0 * P.cc / P.cd, -1.0, Y + j * ldy, skip, per_level);
+            }
+        } else {
+            launch_level<T>(c, v, yin, sc, nullptr, nullptr, 1.0 / P.sigma, 0.0, 0.0, Y + j * ldy,
+                            skip, per_level);
+        }
+    }
+}
+
+template <typename TR>
+inline void launch_residual(Ctx& c, const StencilView& v, const double* f, const double* x, TR* r,
+                            double* part) {
+    c.begin(SSTEP_K_RESID, (double)v.N * (16.0 + sizeof(TR)));
+    const int nseg = stencil_segments(v);
+    hipLaunchKernelGGL(k_residual<TR>, dim3((unsigned)stencil_blocks(v)), dim3(kThreads), 0, c.st,
+                       v, nseg, f, x, r, part);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+// Gram geometry: column-tile width for a given Z width, and the point chunk.
+constexpr int gram_ca_c(int kz) { return kz <= 2 ? 8 : (kz <= 9 ? 4 : 2); }
+inline int gram_ca(int kz) { return gram_ca_c(kz); }
+inline int gram_kz(int nz) {
+    static const int ks[] = {1, 2, 4, 8, 9, 12, 13, 16, 17};
+    for (int k : ks)
+        if (nz <= k) return k;
+    return -1;
+}
+inline void gram_geometry(long long N, int ncx, int nz, int* KZ, int* CA, int* nct, int* nchunk,
+                          long long* chunk) {
+    *KZ = gram_kz(nz);
+    *CA = gram_ca(*KZ);
+    *nct = (ncx + *CA - 1) / *CA;
+    long long nch = std::min<long long>((N + 8191) / 8192, std::max(1, 4096 / *nct));
+    nch = std::max<long long>(1, std::min<long long>(nch, 512));
+    long long ck = round_up((N + nch - 1) / nch, 512);
+    nch = (N + ck - 1) / ck;
+    *nchunk = (int)std::max<long long>(nch, 1);
+    *chunk = ck;
+}
+inline size_t gram_partial_doubles(long long N, int ncx, int nz) {
+    int KZ, CA, nct, nchunk;
+    long long chunk;
+    gram_geometry(N, ncx, nz, &KZ, &CA, &nct, &nchunk, &chunk);
+    return (size_t)nchunk * ncx * KZ;
+}
+
+template <typename T, int CA, int KZ>
+inline void gram_go(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
+                    int nz1, const T* Z2, long long ldz2, int nz2, long long N, long long chunk,
+                    int nct, int nchunk, double* part, const int* skip) {
+    hipLaunchKernelGGL((k_gram_partial<T, CA, KZ>), dim3((unsigned)(nct * nchunk)), dim3(kThreads),
+                       0, c.st, X, ldx, ncx, Z1, ldz1, nz1, Z2, ldz2, nz2, N, chunk, nct, part,
+                       skip);
+}
+
+// G (ncx x (nz1+nz2), row-major) = X^T [Z1 | Z2]
+template <typename T>
+inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
+                        int nz1, const T* Z2, long long ldz2, int nz2, long long N, double* part,
+                        double* G, const int* skip) {
+    const int nz = nz1 + nz2;
+    int KZ, CA, nct, nchunk;
+    long long chunk;
+    gram_geometry(N, ncx, nz, &KZ, &CA, &nct, &nchunk, &chunk);
+    c.begin(SSTEP_K_GRAM, (double)N * sizeof(T) * (ncx + nz));
+    if (!Z2) Z2 = Z1;
+#define SSTEP_GRAM_CASE(K)                                                                      \
+    case K:                                                                                     \
+        gram_go<T, gram_ca_c(K), K>(c, X, ldx, ncx, Z1, ldz1, nz1, Z2, ldz2, nz2, N, chunk, nct, \
+                                    nchunk, part, skip);                                        \
+        break;
+    switch (KZ) {
+        SSTEP_GRAM_CASE(1)
+        SSTEP_GRAM_CASE(2)
+        SSTEP_GRAM_CASE(4)
+        SSTEP_GRAM_CASE(8)
+        SSTEP_GRAM_CASE(9)
+        SSTEP_GRAM_CASE(12)
+        SSTEP_GRAM_CASE(13)
+        SSTEP_GRAM_CASE(16)
+        SSTEP_GRAM_CASE(17)
+        default:
+            throw HipFailure{hipErrorInvalidValue, "gram width"};
+    }
+#undef SSTEP_GRAM_CASE
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+    c.begin(SSTEP_K_GRAM, 0.0);
+    const int nout = ncx * nz;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((nout + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       c.st, part, nchunk, ncx, KZ, nz, G, skip);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+inline long long update_blocks(long long N) { return (N + 2 * kThreads - 1) / (2 * kThreads); }
+
+// out[:, l] = base[:, l] + sum_c V[:, c] M[c*nout + l]
+template <typename TV, typename TB, typename TO, typename TA, bool NORM>
+inline void launch_update(Ctx& c, long long N, const TB* base, long long ldb, const TV* V,
+                          long long ldv, int n2, const int* n2_dev, const double* M, TO* out,
+                          long long ldo, int nout, double* part, const int* skip, double bytes,
+                          int cls = SSTEP_K_UPDATE) {
+    c.begin(cls, bytes);
+    const dim3 g((unsigned)update_blocks(N));
+#define SSTEP_UPD(K)                                                                          \
+    hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM>), g, dim3(kThreads), 0, c.st, N, base, \
+                       ldb, V, ldv, n2, n2_dev, M, out, ldo, nout, part, skip)
+    if (nout <= 1) SSTEP_UPD(1);
+    else if (nout <= 2) SSTEP_UPD(2);
+    else if (nout <= 4) SSTEP_UPD(4);
+    else if (nout <= 8) SSTEP_UPD(8);
+    else if (nout <= 12) SSTEP_UPD(12);
+    else SSTEP_UPD(16);
+#undef SSTEP_UPD
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+}  // namespace sstep

@@ -1,0 +1,271 @@
+"""Python binding of libsstep.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers and the current HIP stream, and fills the C
+structs of ``include/sstep.h``.  It raises if the library is missing or fails
+to load -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsstep.so")
+
+OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = 0, 1, -1, -2, -3, -4, -5
+MONOMIAL, CHEBYSHEV = 0, 1
+FP64, MIXED = 0, 1
+METHOD_OMIN, METHOD_GMRES = 0, 1
+K_MPK, K_GRAM, K_UPDATE, K_RESID, K_SCALAR, K_NCLASS = 0, 1, 2, 3, 4, 5
+KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar")
+
+# every symbol declared in include/sstep.h
+EXPORTS = (
+    "sstep_default_options", "sstep_status_string", "sstep_workspace_bytes",
+    "sstep_gmres_solve", "sstep_omin_solve", "sstep_stencil_apply",
+    "sstep_kernel_mpk", "sstep_kernel_gram", "sstep_kernel_update",
+)
+
+
+class StencilC(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("c", C.c_double * 7), ("coef", C.c_void_p)]
+
+
+class OptionsC(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("basis", C.c_int32),
+                ("profile", C.c_int32), ("sigma", C.c_double), ("inner_tol", C.c_double),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class InfoC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32),
+                ("matvecs", C.c_int32), ("rel_resid", C.c_double), ("rel_resid_est", C.c_double),
+                ("sigma", C.c_double), ("cheb_centre", C.c_double),
+                ("cheb_half_width", C.c_double), ("ms_total", C.c_double),
+                ("launches", C.c_int64 * K_NCLASS), ("ms", C.c_double * K_NCLASS),
+                ("bytes", C.c_double * K_NCLASS)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libsstep.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library {p} is missing: run __graft_entry__.build() first")
+    lib = C.CDLL(p)
+    vp, dp, i32, i64 = C.c_void_p, C.c_double, C.c_int, C.c_int64
+    sp, op_, ip = C.POINTER(StencilC), C.POINTER(OptionsC), C.POINTER(InfoC)
+    lib.sstep_default_options.argtypes = [op_]
+    lib.sstep_default_options.restype = None
+    lib.sstep_status_string.argtypes = [i32]
+    lib.sstep_status_string.restype = C.c_char_p
+    lib.sstep_workspace_bytes.argtypes = [sp, i32, i32, i32, i32]
+    lib.sstep_workspace_bytes.restype = C.c_size_t
+    lib.sstep_gmres_solve.argtypes = [sp, vp, vp, i32, i32, dp, op_, ip]
+    lib.sstep_gmres_solve.restype = i32
+    lib.sstep_omin_solve.argtypes = [sp, vp, vp, i32, i32, dp, op_, ip]
+    lib.sstep_omin_solve.restype = i32
+    lib.sstep_stencil_apply.argtypes = [sp, vp, vp, vp]
+    lib.sstep_stencil_apply.restype = i32
+    lib.sstep_kernel_mpk.argtypes = [sp, vp, i64, i32, i32, dp, dp, dp, dp, vp]
+    lib.sstep_kernel_mpk.restype = i32
+    lib.sstep_kernel_gram.argtypes = [vp, i64, i32, vp, i64, i32, i64, vp, vp]
+    lib.sstep_kernel_gram.restype = i32
+    lib.sstep_kernel_update.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp]
+    lib.sstep_kernel_update.restype = i32
+    _lib = lib
+    return lib
+
+
+def status_string(st: int) -> str:
+    return load().sstep_status_string(int(st)).decode()
+
+
+class SstepError(RuntimeError):
+    pass
+
+
+def _check(st: int, what: str):
+    if st < 0:
+        raise SstepError(f"{what}: {status_string(st)} ({st})")
+    return st
+
+
+@dataclass
+class Stencil:
+    """Stencil operator descriptor (include/sstep.h sstep_stencil).  ``coef``,
+    if given, is a CUDA float64 tensor [7, N] that must outlive the calls."""
+    ndim: int
+    nx: int
+    ny: int
+    nz: int = 1
+    c: tuple = (0.0,) * 7
+    coef: object = None
+
+    @classmethod
+    def from_problem(cls, prob, coef_device=None):
+        return cls(prob.ndim, prob.nx, prob.ny, prob.nz, tuple(float(v) for v in prob.c),
+                   coef_device)
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * (self.nz if self.ndim == 3 else 1)
+
+    def c_struct(self) -> StencilC:
+        s = StencilC()
+        s.ndim, s.nx, s.ny, s.nz = self.ndim, self.nx, self.ny, self.nz if self.ndim == 3 else 1
+        for q in range(7):
+            s.c[q] = float(self.c[q])
+        s.coef = _ptr(self.coef) if self.coef is not None else None
+        return s
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    cycles: int
+    matvecs: int
+    rel_resid: float
+    rel_resid_est: float
+    sigma: float
+    cheb_centre: float
+    cheb_half_width: float
+    ms_total: float
+    launches: dict
+    ms: dict
+    bytes: dict
+
+    @classmethod
+    def from_c(cls, i: InfoC):
+        return cls(i.status, i.iters, i.cycles, i.matvecs, i.rel_resid, i.rel_resid_est, i.sigma,
+                   i.cheb_centre, i.cheb_half_width, i.ms_total,
+                   {k: int(i.launches[n]) for n, k in enumerate(KERNEL_CLASSES)},
+                   {k: float(i.ms[n]) for n, k in enumerate(KERNEL_CLASSES)},
+                   {k: float(i.bytes[n]) for n, k in enumerate(KERNEL_CLASSES)})
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dim() > 0 and t.stride(-1) != 1:
+        raise ValueError("tensor rows must be contiguous")
+    return t.data_ptr()
+
+
+def _f64(t, n, name):
+    import torch
+    if t.dtype != torch.float64 or t.numel() < n:
+        raise ValueError(f"{name} must be a float64 tensor with >= {n} elements")
+    return _ptr(t)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
+            workspace=None, stream=None) -> OptionsC:
+    o = OptionsC()
+    load().sstep_default_options(C.byref(o))
+    o.max_iters = int(max_iters)
+    o.precision = int(precision)
+    o.basis = int(basis)
+    o.profile = 1 if profile else 0
+    o.sigma = float(sigma)
+    o.inner_tol = float(inner_tol)
+    if workspace is not None:
+        o.workspace = _ptr(workspace)
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.stream = _stream(stream)
+    return o
+
+
+def workspace_bytes(A: Stencil, method: int, s: int, k_or_m: int, precision: int = FP64) -> int:
+    sc = A.c_struct()
+    return int(load().sstep_workspace_bytes(C.byref(sc), method, s, k_or_m, precision))
+
+
+def allocate_workspace(A: Stencil, method: int, s: int, k_or_m: int, precision: int = FP64,
+                       device="cuda"):
+    """A caller-owned workspace tensor (uint8) large enough for the solver."""
+    import torch
+    nb = workspace_bytes(A, method, s, k_or_m, precision)
+    if nb == 0:
+        raise SstepError("invalid arguments for workspace sizing")
+    return torch.empty(nb + 256, dtype=torch.uint8, device=device)[: nb]
+
+
+def gmres_solve(A: Stencil, f, x, s: int, m: int, tol: float, **kw) -> Info:
+    """s-step GMRES(m) (Sec. 4, Alg. 4.2); x (in: x0, out: solution) updated in place."""
+    sc = A.c_struct()
+    info = InfoC()
+    o = options(**kw)
+    load().sstep_gmres_solve(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, m, tol,
+                             C.byref(o), C.byref(info))
+    return Info.from_c(info)
+
+
+def omin_solve(A: Stencil, f, x, s: int, k: int, tol: float, **kw) -> Info:
+    """s-step Orthomin(k) (Sec. 3, Alg. 3.1); x updated in place."""
+    sc = A.c_struct()
+    info = InfoC()
+    o = options(**kw)
+    load().sstep_omin_solve(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, k, tol,
+                            C.byref(o), C.byref(info))
+    return Info.from_c(info)
+
+
+def stencil_apply(A: Stencil, x, y, stream=None) -> None:
+    """y = A x."""
+    sc = A.c_struct()
+    _check(load().sstep_stencil_apply(C.byref(sc), _f64(x, A.N, "x"), _f64(y, A.N, "y"),
+                                      _stream(stream)), "stencil_apply")
+
+
+def kernel_mpk(A: Stencil, Y, s: int, basis=MONOMIAL, in_scale=1.0, sigma=1.0, cheb_c=0.0,
+               cheb_d=1.0, stream=None) -> None:
+    """Matrix powers of Y[0] into Y[1..s]; Y is a (s+1, ld) float64 tensor."""
+    sc = A.c_struct()
+    if Y.dim() != 2 or Y.shape[0] < s + 1:
+        raise ValueError("Y must be (s+1, ld)")
+    _check(load().sstep_kernel_mpk(C.byref(sc), _f64(Y, (s + 1) * A.N, "Y"), Y.stride(0), s, basis,
+                                   in_scale, sigma, cheb_c, cheb_d, _stream(stream)), "kernel_mpk")
+
+
+def kernel_gram(X, Z, G=None, stream=None):
+    """G = X^T Z (X: (ncx, ld), Z: (ncz, ld) float64; rows are columns of the
+    tall-skinny blocks).  Returns G (ncx, ncz) on the device."""
+    import torch
+    ncx, ncz, N = X.shape[0], Z.shape[0], X.shape[1]
+    if G is None:
+        G = torch.empty((ncx, ncz), dtype=torch.float64, device=X.device)
+    _check(load().sstep_kernel_gram(_f64(X, ncx * N, "X"), X.stride(0), ncx, _f64(Z, ncz * N, "Z"),
+                                    Z.stride(0), ncz, N, _f64(G, ncx * ncz, "G"), _stream(stream)),
+           "kernel_gram")
+    return G
+
+
+def kernel_update(X, Y, M, stream=None) -> None:
+    """Y[l] += sum_c X[c] M[c, l] (X: (ncx, ld), Y: (ncy, ld), M: (ncx, ncy) float64, device)."""
+    ncx, ncy, N = X.shape[0], Y.shape[0], Y.shape[1]
+    xp = _f64(X, ncx * N, "X") if ncx else None
+    mp = _f64(M, ncx * ncy, "M") if ncx else None
+    _check(load().sstep_kernel_update(xp, X.stride(0) if ncx else N, ncx, _f64(Y, ncy * N, "Y"),
+                                      Y.stride(0), ncy, mp, N, _stream(stream)), "kernel_update")
