@@ -12,7 +12,8 @@
  *
  * Conventions that hold for every entry point:
  *   - Every N-length array is a DEVICE pointer owned by the caller, FP64,
- *     contiguous, x-fastest lexicographic order p = i + nx*(j + ny*l).
+ *     contiguous, 16-byte aligned, x-fastest lexicographic order
+ *     p = i + nx*(j + ny*l).  Column blocks (primitives) have an even stride.
  *     The library never frees caller memory and keeps no pointer after the
  *     call returns.
  *   - Host structs are read only during the call.

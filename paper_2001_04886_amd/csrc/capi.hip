@@ -140,7 +140,8 @@ int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s,
                       double tol, const sstep_options* opt, sstep_info* info) {
     const int prec = opt ? opt->precision : SSTEP_FP64;
     const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
-    if (!stencil_ok(A) || !f || !x || s < 1 || s > kMaxS || m < 1 || (long long)m * s > 2048 ||
+    if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
+        s > kMaxS || m < 1 || (long long)m * s > 2048 ||
         !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
         (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
         (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0)))) {
@@ -158,7 +159,8 @@ int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, 
                      const sstep_options* opt, sstep_info* info) {
     const int prec = opt ? opt->precision : SSTEP_FP64;
     const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
-    if (!stencil_ok(A) || !f || !x || s < 1 || s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
+    if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
+        s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
         prec != SSTEP_FP64 || (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
         (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0)))) {
         if (info) std::memset(info, 0, sizeof(*info));
@@ -229,6 +231,8 @@ int sstep_kernel_update(const double* X, int64_t ldx, int ncx, double* Y, int64_
                         const double* M, int64_t N, void* stream) {
     if ((ncx > 0 && (!X || !M || ldx < N)) || !Y || N < 1 || ncx < 0 || ncy < 1 || ncy > 16 ||
         ldy < N || N > (1LL << 31) - 1)
+        return SSTEP_ERR_ARG;
+    if ((ncx > 0 && (((uintptr_t)X & 15u) || (ldx & 1))) || ((uintptr_t)Y & 15u) || (ldy & 1))
         return SSTEP_ERR_ARG;
     return guarded(nullptr, [&]() -> int {
         Ctx c;

@@ -160,68 +160,97 @@ __global__ __launch_bounds__(kThreads) void k_gm_proj(GmArrays a) {
 }
 
 // Scalar1 (Sec. 4): factor W_k = Vbar_k^T Vbar_k, g = W_k^{-1} Vbar_k^T Yhat_s.
-// Gb is the Gram of the stored columns [w_hat_k, y_1..y_s] (s+1 square).
+// Gout is the Gram of the stored columns [w_hat_k, y_1..y_s] (s+1 square).
 // A rank-deficient W_k (pivot below rank_tol) truncates the block to its
 // leading q columns; column q then plays the role of Yhat_s with nu = 0.
-__global__ void k_gm_block(GmArrays a) {
+// Factor work happens in LDS (one thread), then the factor is copied out.
+__global__ __launch_bounds__(64) void k_gm_block(GmArrays a) {
+    __shared__ GramFactor F;
+    __shared__ double W[kMaxS * kMaxS];
     GmState* st = a.st;
-    if (st->done || threadIdx.x != 0) return;
+    if (st->done) return;
     const int s = st->s, kb = st->kb, s1 = s + 1;
     const double d0 = st->inv_nu[kb];
-    double W[kMaxS * kMaxS];
-    for (int q = 0; q < s; ++q)
-        for (int p = 0; p < s; ++p)
-            W[p + q * kMaxS] = a.Gout[p * s1 + q] * (p == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
-    st->yhat2 = a.Gout[s * s1 + s];
-    GramFactor* F = &a.Wf[kb];
-    gram_factor(W, kMaxS, s, st->rank_tol, F);
-    const int q = F->rank;
-    if (q == s) {
-        double h[kMaxS];
-        for (int p = 0; p < s; ++p) h[p] = a.Gout[p * s1 + s] * (p == 0 ? d0 : 1.0);
-        gram_solve(*F, h, st->g);
-        for (int p = 0; p < s; ++p) st->coefN4b[p] = -st->g[p] * (p == 0 ? d0 : 1.0);
-        st->skip_n4b = 0;
-    } else if (q > 0) {
-        double h[kMaxS];
-        for (int p = 0; p < q; ++p) h[p] = W[p + q * kMaxS];
-        gram_solve_leading(*F, q, h, st->g);
-        st->skip_n4b = 1;
-    } else {
-        st->err = SSTEP_ERR_NONFINITE;
-        st->done = 1;
-        st->skip_n4b = 1;
+    for (int idx = threadIdx.x; idx < s * s; idx += 64) {
+        const int p = idx % s, q = idx / s;
+        W[p + q * kMaxS] = a.Gout[p * s1 + q] * (p == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->yhat2 = a.Gout[s * s1 + s];
+        gram_factor(W, kMaxS, s, st->rank_tol, &F);
+        const int q = F.rank;
+        if (q == s) {
+            double h[kMaxS];
+            for (int p = 0; p < s; ++p) h[p] = a.Gout[p * s1 + s] * (p == 0 ? d0 : 1.0);
+            gram_solve(F, h, st->g);
+            for (int p = 0; p < s; ++p) st->coefN4b[p] = -st->g[p] * (p == 0 ? d0 : 1.0);
+            st->skip_n4b = 0;
+        } else if (q > 0) {
+            double h[kMaxS];
+            for (int p = 0; p < q; ++p) h[p] = W[p + q * kMaxS];
+            gram_solve_leading(F, q, h, st->g);
+            st->skip_n4b = 1;
+        } else {
+            st->err = SSTEP_ERR_NONFINITE;
+            st->done = 1;
+            st->skip_n4b = 1;
+        }
+    }
+    __syncthreads();
+    // copy the factor out
+    const double* src = reinterpret_cast<const double*>(&F);
+    double* dst = reinterpret_cast<double*>(&a.Wf[kb]);
+    for (int i = threadIdx.x; i < (int)(sizeof(GramFactor) / sizeof(double)); i += 64) dst[i] = src[i];
+}
+
+// nu_k = ||w_hat|| from the partial sums of the N4b pass (0 for a truncated
+// block) and the lucky-breakdown test.
+__global__ __launch_bounds__(kThreads) void k_gm_nu(GmArrays a, const double* __restrict__ part,
+                                                    int npart) {
+    __shared__ double lds[4];
+    GmState* st = a.st;
+    if (st->done) return;
+    const int s = st->s, q = a.Wf[st->kb].rank;
+    double acc = 0.0;
+    if (q == s)
+        for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
+    double v[1] = {acc}, o[1];
+    block_sum<1>(v, lds, o);
+    if (threadIdx.x == 0) {
+        const double nu = q == s ? sqrt(o[0]) : 0.0;
+        st->nu_cur = nu;
+        st->lucky = (q == s) && !(nu > st->lucky_tol * sqrt(st->yhat2));
     }
 }
 
-// Hessenberg block column (eq. (5)), L scaling with D = L^T L (eq. (7)),
-// Givens QR and the least-squares residual estimate.  In coordinates of
-// U = [Vbar_1 .. Vbar_k, w_{k+1}]:  Y = U Z_k with
+// Hessenberg block column (eq. (5)) and its L scaling (eq. (7)).  In
+// coordinates of U = [Vbar_1 .. Vbar_k, w_{k+1}]:  Y = U Z_k with
 //   Z_k = [T_1; ..; T_{k-1}; [I | g]; nu e^T],
-//   Gbar[:, block k] = Z_k B - sum_{i<k} Gbar[:, block i] T_i[:, 0:s].
-__global__ __launch_bounds__(kThreads) void k_gm_hess(GmArrays a, const double* __restrict__ part,
-                                                      int npart) {
-    __shared__ double lds[4];
-    __shared__ double nu_sh;
+//   Gbar[:, block k] = Z_k B - sum_{i<k} Gbar[:, block i] T_i[:, 0:s],
+// then rows of block i are multiplied by the upper Cholesky factor L_i of
+// W_i (D = L^T L).  Workgroup i handles the rows of block i (workgroup kb
+// also the row of w_{k+1}).
+__global__ __launch_bounds__(kThreads) void k_gm_hess_cols(GmArrays a) {
+    __shared__ double gs[(kMaxS + 1) * kMaxS];
+    __shared__ GramFactor F;
     GmState* st = a.st;
     if (st->done) return;
     const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
     const int q = a.Wf[kb].rank;
-    if (q == s) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
-        double v[1] = {acc}, o[1];
-        block_sum<1>(v, lds, o);
-        if (threadIdx.x == 0) nu_sh = sqrt(o[0]);
-    } else if (threadIdx.x == 0) {
-        nu_sh = 0.0;
-    }
-    __syncthreads();
-    const double nu = nu_sh;
+    const int bi = blockIdx.x;                 // row block
+    const int r0 = bi * s;
+    const int nr = (bi < kb) ? s : q + 1;      // rows handled
+    const double nu = st->nu_cur;
     const double* Bc = st->Bc;
-    // Hessenberg columns c0 .. c0+q-1, rows 0 .. c0+q
-    for (int idx = threadIdx.x; idx < q * (c0 + q + 1); idx += kThreads) {
-        const int j = idx / (c0 + q + 1), r = idx % (c0 + q + 1);
+    {
+        const double* src = reinterpret_cast<const double*>(&a.Wf[bi < kb ? bi : kb]);
+        double* dst = reinterpret_cast<double*>(&F);
+        for (int i = threadIdx.x; i < (int)(sizeof(GramFactor) / sizeof(double)); i += kThreads)
+            dst[i] = src[i];
+    }
+    for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
+        const int rr = idx % nr, j = idx / nr, r = r0 + rr;
         double val = 0.0;
         for (int l = 0; l <= q; ++l) {
             const double bl = Bc[l + j * (s + 1)];
@@ -239,45 +268,53 @@ __global__ __launch_bounds__(kThreads) void k_gm_hess(GmArrays a, const double* 
             }
         }
         a.G[r + (long long)(c0 + j) * ldg] = val;
+        gs[rr + j * (kMaxS + 1)] = val;
     }
     __syncthreads();
-    // L scaling of the new columns
-    for (int idx = threadIdx.x; idx < q * (c0 + q + 1); idx += kThreads) {
-        const int j = idx / (c0 + q + 1), r = idx % (c0 + q + 1);
-        const double* gc = a.G + (long long)(c0 + j) * ldg;
+    // L scaling: rows of block bi (rank qi), plus the unit row of w_{k+1}
+    const int qi = (bi < kb) ? s : q;
+    for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
+        const int rr = idx % nr, j = idx / nr;
         double val;
-        if (r == c0 + q) {
-            val = gc[r];
+        if (bi == kb && rr == q) {
+            val = gs[rr + j * (kMaxS + 1)];
         } else {
-            const int i = r / s, p = r % s;
-            const int qi = (i < kb) ? s : q;
-            const GramFactor& F = a.Wf[i];
             val = 0.0;
-            for (int b = p; b < qi; ++b) val += gram_L(F, p, b) * gc[i * s + b];
+            for (int b = rr; b < qi; ++b) val += gram_L(F, rr, b) * gs[b + j * (kMaxS + 1)];
         }
-        a.R[r + (long long)(c0 + j) * ldg] = val;
+        a.R[r0 + rr + (long long)(c0 + j) * ldg] = val;
     }
-    __syncthreads();
-    // rotations of earlier columns, one thread per new column
-    if ((int)threadIdx.x < q) {
-        double* rc = a.R + (long long)(c0 + threadIdx.x) * ldg;
+}
+
+// Givens QR of the new columns of L Gbar and the least-squares residual
+// estimate |rhs[ncols]|; stopping tests of the block.
+__global__ __launch_bounds__(64) void k_gm_givens(GmArrays a) {
+    GmState* st = a.st;
+    if (st->done) return;
+    const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
+    const int q = a.Wf[kb].rank;
+    if ((int)threadIdx.x < q) {  // earlier rotations, one thread per new column
+        double* col = a.R + (long long)(c0 + threadIdx.x) * ldg;
+        double x0 = col[0];
+#pragma unroll 8
         for (int i = 0; i < c0; ++i) {
-            const double x0 = rc[i], x1 = rc[i + 1];
-            rc[i] = a.cs[i] * x0 + a.sn[i] * x1;
-            rc[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
+            const double cth = a.cs[i], sth = a.sn[i], x1 = col[i + 1];
+            col[i] = cth * x0 + sth * x1;
+            x0 = -sth * x0 + cth * x1;
         }
+        col[c0] = x0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int j = 0; j < q; ++j) {
-            double* rc = a.R + (long long)(c0 + j) * ldg;
+            double* col = a.R + (long long)(c0 + j) * ldg;
             for (int i = c0; i < c0 + j; ++i) {
-                const double x0 = rc[i], x1 = rc[i + 1];
-                rc[i] = a.cs[i] * x0 + a.sn[i] * x1;
-                rc[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
+                const double x0 = col[i], x1 = col[i + 1];
+                col[i] = a.cs[i] * x0 + a.sn[i] * x1;
+                col[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
             }
             const int cj = c0 + j;
-            const double x0 = rc[cj], x1 = rc[cj + 1];
+            const double x0 = col[cj], x1 = col[cj + 1];
             double cth = 1.0, sth = 0.0;
             if (x1 != 0.0) {
                 const double h = hypot(x0, x1);
@@ -286,28 +323,27 @@ __global__ __launch_bounds__(kThreads) void k_gm_hess(GmArrays a, const double* 
             }
             a.cs[cj] = cth;
             a.sn[cj] = sth;
-            rc[cj] = cth * x0 + sth * x1;
-            rc[cj + 1] = 0.0;
+            col[cj] = cth * x0 + sth * x1;
+            col[cj + 1] = 0.0;
             const double g0 = a.rhs[cj];
             a.rhs[cj + 1] = -sth * g0;
             a.rhs[cj] = cth * g0;
         }
         const double est = fabs(a.rhs[c0 + q]);
+        const double nu = st->nu_cur;
         st->est = est;
         st->ncols = c0 + q;
         st->kb = kb + 1;
         st->blocks_total += 1;
         st->nu[kb + 1] = nu;
         st->inv_nu[kb + 1] = nu > 0.0 ? 1.0 / nu : 0.0;
-        const bool lucky = (q == s) && !(nu > st->lucky_tol * sqrt(st->yhat2));
         if (!isfinite(est)) {
             st->err = SSTEP_ERR_NONFINITE;
             st->done = 1;
-        } else if (est <= st->stop_abs || lucky || q < s || kb + 1 == st->m) {
+        } else if (est <= st->stop_abs || st->lucky || q < s || kb + 1 == st->m) {
             st->done = 1;
         }
         if (st->done) st->skip_n4b = 1;
-        st->lucky = lucky;
     }
 }
 
@@ -375,7 +411,7 @@ static GmLayout gm_layout(const sstep_stencil& A, int s, int m, int precision) {
     size_t gp = gram_partial_doubles(L.N, s + 1, s + 1);
     for (int ncx = s; ncx < K; ncx += s) gp = std::max(gp, gram_partial_doubles(L.N, ncx, s));
     L.off_gpart = take(sizeof(double) * gp);
-    L.off_npart = take(sizeof(double) * (size_t)update_blocks(L.N));
+    L.off_npart = take(sizeof(double) * (size_t)std::max<long long>(update_blocks(L.N), norm_blocks(L.N)));
     const StencilView v = make_view(A);
     L.off_rpart = take(sizeof(double) * (size_t)stencil_blocks(v));
     L.off_scratch = take(sizeof(double) * 64 * 3);
@@ -439,19 +475,14 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
     const double vb = (double)N * sizeof(T);
 
     // ||f||
-    {
-        c.cur_block = -1;
-        launch_update<double, double, T, double, true>(c, N, f, 0, (const double*)nullptr, 0, 0,
-                                                       nullptr, nullptr, basis, ld, 1, npart,
-                                                       nullptr, 8.0 * N + vb, SSTEP_K_SCALAR);
-        c.begin(SSTEP_K_SCALAR, 0.0);
-        hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kThreads), 0, c.st, a, npart,
-                           (int)update_blocks(N));
-        SSTEP_HIP(hipGetLastError());
-        c.end();
-    }
+    c.cur_block = -1;
+    launch_norm2(c, N, f, npart);
+    c.begin(SSTEP_K_SCALAR, 0.0);
+    hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kThreads), 0, c.st, a, npart, norm_blocks(N));
+    SSTEP_HIP(hipGetLastError());
+    c.end();
     const int nrpart = (int)stencil_blocks(v);
-    const int nnpart = (int)update_blocks(N);
+    const int nnpart = (int)update_blocks_t<T, T, T>(N);
     auto residual_and_start = [&]() {
         c.cur_block = -1;
         launch_residual<T>(c, v, f, x, basis, rpart);
@@ -519,7 +550,9 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
                                             dst->coefN4b, Yk + (long long)s * ld, ld, 1, npart,
                                             &dst->skip_n4b, vb * (s + 2));
             c.begin(SSTEP_K_SCALAR, 0.0);
-            hipLaunchKernelGGL(k_gm_hess, dim3(1), dim3(kThreads), 0, c.st, a, npart, nnpart);
+            hipLaunchKernelGGL(k_gm_nu, dim3(1), dim3(kThreads), 0, c.st, a, npart, nnpart);
+            hipLaunchKernelGGL(k_gm_hess_cols, dim3(kb + 1), dim3(kThreads), 0, c.st, a);
+            hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, c.st, a);
             SSTEP_HIP(hipGetLastError());
             c.end();
         }

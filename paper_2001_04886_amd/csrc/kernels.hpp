@@ -147,13 +147,45 @@ __global__ __launch_bounds__(kThreads) void k_residual(StencilView A, int nseg,
 }
 
 // ---------------------------------------------------------------------------
+// 16-byte vector access helpers.  NT: non-temporal (streamed once; keeps the
+// L2 for data that is re-read).
+// ---------------------------------------------------------------------------
+template <typename T, int PPT, bool NT>
+__device__ __forceinline__ void load_pts(const T* __restrict__ p, T (&v)[PPT]) {
+    constexpr int E = 16 / sizeof(T);
+    static_assert(PPT % E == 0, "points per thread must fill 16-byte loads");
+    typedef T vt __attribute__((ext_vector_type(E)));
+#pragma unroll
+    for (int q = 0; q < PPT / E; ++q) {
+        vt t;
+        if constexpr (NT) t = __builtin_nontemporal_load(reinterpret_cast<const vt*>(p + q * E));
+        else t = *reinterpret_cast<const vt*>(p + q * E);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q * E + e] = t[e];
+    }
+}
+template <typename T, int PPT>
+__device__ __forceinline__ void store_pts(T* __restrict__ p, const T (&v)[PPT]) {
+    constexpr int E = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(E)));
+#pragma unroll
+    for (int q = 0; q < PPT / E; ++q) {
+        vt t;
+#pragma unroll
+        for (int e = 0; e < E; ++e) t[e] = v[q * E + e];
+        *reinterpret_cast<vt*>(p + q * E) = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Block Gram, stage 1: for a point chunk and a tile of CA columns of X,
 //   partial[chunk][c][j] = sum_{p in chunk} X[c][p] * Z[j][p],  j < KZ
 // Z = [Z1 (nz1 columns) | Z2 (nz2 columns)], nz1 + nz2 <= KZ.  Accumulation
-// in FP64.  Workgroups of one chunk are consecutive on one XCD, so Z is read
-// from HBM once and then served by that XCD's L2.
+// in FP64.  The workgroups of one chunk are consecutive on one XCD, so Z is
+// read from HBM once and then served by that XCD's L2; X is streamed with
+// non-temporal loads.  PPT points per thread per step.
 // ---------------------------------------------------------------------------
-template <typename T, int CA, int KZ>
+template <typename T, int CA, int KZ, int PPT>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(
     const T* __restrict__ X, long long ldx, int ncx, const T* __restrict__ Z1, long long ldz1,
     int nz1, const T* __restrict__ Z2, long long ldz2, int nz2, long long N, long long chunk,
@@ -181,50 +213,46 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(
 #pragma unroll
     for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : c0) * ldx;
 
-    // two consecutive points per thread per step (16-byte loads for FP64)
-    for (long long p = p0 + 2 * threadIdx.x; p < p1; p += 2 * kThreads) {
-        if (p + 1 < p1) {
-            double z0[KZ], z1[KZ];
+    // full vectors: chunk starts are multiples of 512 points
+    const long long pv1 = p0 + (p1 - p0) / PPT * PPT;
+    for (long long p = p0 + (long long)PPT * threadIdx.x; p < pv1; p += (long long)PPT * kThreads) {
+        double zv[KZ][PPT];
 #pragma unroll
-            for (int jz = 0; jz < KZ; ++jz) {
-                if (jz < nz) {
-                    if constexpr (sizeof(T) == 8) {
-                        const double2 v = *reinterpret_cast<const double2*>(zc[jz] + p);
-                        z0[jz] = v.x; z1[jz] = v.y;
-                    } else {
-                        const float2 v = *reinterpret_cast<const float2*>(zc[jz] + p);
-                        z0[jz] = v.x; z1[jz] = v.y;
-                    }
-                } else {
-                    z0[jz] = 0.0; z1[jz] = 0.0;
+        for (int jz = 0; jz < KZ; ++jz) {
+            if (jz < nz) {
+                T t[PPT];
+                load_pts<T, PPT, false>(zc[jz] + p, t);
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) zv[jz][e] = (double)t[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) zv[jz][e] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < CA; ++a) {
+            if (c0 + a < ncx) {
+                T t[PPT];
+                load_pts<T, PPT, true>(xc[a] + p, t);
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) {
+                    const double xv = (double)t[e];
+#pragma unroll
+                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(xv, zv[jz][e], acc[a][jz]);
                 }
             }
+        }
+    }
+    for (long long p = pv1 + threadIdx.x; p < p1; p += kThreads) {  // ragged tail
+        double z0[KZ];
 #pragma unroll
-            for (int a = 0; a < CA; ++a) {
-                if (c0 + a < ncx) {
-                    double x0, x1;
-                    if constexpr (sizeof(T) == 8) {
-                        const double2 v = *reinterpret_cast<const double2*>(xc[a] + p);
-                        x0 = v.x; x1 = v.y;
-                    } else {
-                        const float2 v = *reinterpret_cast<const float2*>(xc[a] + p);
-                        x0 = v.x; x1 = v.y;
-                    }
+        for (int jz = 0; jz < KZ; ++jz) z0[jz] = jz < nz ? to_f64(zc[jz][p]) : 0.0;
 #pragma unroll
-                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], fma(x1, z1[jz], acc[a][jz]));
-                }
-            }
-        } else {
-            double z0[KZ];
+        for (int a = 0; a < CA; ++a) {
+            if (c0 + a < ncx) {
+                const double x0 = to_f64(xc[a][p]);
 #pragma unroll
-            for (int jz = 0; jz < KZ; ++jz) z0[jz] = jz < nz ? to_f64(zc[jz][p]) : 0.0;
-#pragma unroll
-            for (int a = 0; a < CA; ++a) {
-                if (c0 + a < ncx) {
-                    const double x0 = to_f64(xc[a][p]);
-#pragma unroll
-                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
-                }
+                for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
             }
         }
     }
@@ -240,94 +268,119 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(
     }
 }
 
-// Block Gram, stage 2: G[c*nz + j] = sum over chunks (fixed order).
+// Block Gram, stage 2: G[c*nz + j] = sum over chunks in a fixed order.
+// 64 outputs per workgroup, 4 threads per output each summing a fixed
+// quarter of the chunks, combined in a fixed order.
 static __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* __restrict__ part,
                                                                  int nchunk, int ncx, int KZ,
                                                                  int nz, double* __restrict__ G,
                                                                  const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int o = blockIdx.x * kThreads + threadIdx.x;
-    if (o >= ncx * nz) return;
-    const int c = o / nz, jz = o % nz;
+    __shared__ double lds[4][64];
+    const int lo = threadIdx.x & 63, qd = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lo;
     double s = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) s += part[((long long)ch * ncx + c) * KZ + jz];
-    G[o] = s;
+    if (o < ncx * nz) {
+        const int c = o / nz, jz = o % nz;
+        const int per = (nchunk + 3) / 4;
+        const int ch0 = qd * per, ch1 = min(nchunk, ch0 + per);
+        double s0 = 0.0, s1 = 0.0;
+        int ch = ch0;
+        for (; ch + 1 < ch1; ch += 2) {
+            s0 += part[((long long)ch * ncx + c) * KZ + jz];
+            s1 += part[((long long)(ch + 1) * ncx + c) * KZ + jz];
+        }
+        if (ch < ch1) s0 += part[((long long)ch * ncx + c) * KZ + jz];
+        s = s0 + s1;
+    }
+    lds[qd][lo] = s;
+    __syncthreads();
+    if (qd == 0 && o < ncx * nz) G[o] = (lds[0][lo] + lds[1][lo]) + (lds[2][lo] + lds[3][lo]);
 }
 
 // ---------------------------------------------------------------------------
 // Block update (tall-skinny linear combination):
-//   out[:, l] = base[:, l] + sum_{c < n2} V[:, c] * M[c * nout + l],  l < nout <= NOUT
-// base has type TB (may alias out: every thread reads all its inputs before
-// writing).  n2 may come from device memory (n2_dev) so a launch can cover a
-// column count that is only known on the device.  Arithmetic in TA.
-// NORM: per-workgroup partial sum of out[:,0]^2 (FP64) into part[blockIdx].
+//   out[:, l] = base[:, l] + sum_{c < n2} V[:, c] * M[c * NOUT + l],  l < NOUT
+// base has type TB (nullptr: zero).  base may alias out and out may alias
+// columns of V: every thread reads all inputs of its points before writing.
+// n2 may come from device memory (n2_dev) so a launch can cover a column count
+// that is only known on the device.  Arithmetic in TA.  V is streamed with
+// non-temporal loads.  NORM: per-workgroup partial sum of out[:,0]^2 (FP64).
 // ---------------------------------------------------------------------------
 template <typename TV, typename TB, typename TO, typename TA, int NOUT, bool NORM>
 __global__ __launch_bounds__(kThreads) void k_update(
     long long N, const TB* base, long long ldb, const TV* V, long long ldv, int n2,
     const int* __restrict__ n2_dev, const double* __restrict__ M, TO* out, long long ldo,
-    int nout, double* __restrict__ part, const int* __restrict__ skip) {
+    double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
+    constexpr int PA = 16 / sizeof(TV), PB = 16 / sizeof(TB), PO = 16 / sizeof(TO);
+    constexpr int PPT = PA > PB ? (PA > PO ? PA : PO) : (PB > PO ? PB : PO);
     const int nc = n2_dev ? *n2_dev : n2;
-    constexpr int PPT = 2;  // points per thread
     const long long p = ((long long)blockIdx.x * kThreads + threadIdx.x) * PPT;
     double nrm = 0.0;
-    if (p < N) {
-        const bool full = p + 1 < N;
+    if (p + PPT <= N) {
         TA acc[NOUT][PPT];
 #pragma unroll
         for (int l = 0; l < NOUT; ++l) {
-            if (base && l < nout) {
-                const TB* bc = base + l * ldb;
-                acc[l][0] = (TA)bc[p];
-                acc[l][1] = full ? (TA)bc[p + 1] : TA(0);
+            if (base) {
+                TB t[PPT];
+                load_pts<TB, PPT, false>(base + l * ldb + p, t);
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) acc[l][e] = (TA)t[e];
             } else {
-                acc[l][0] = acc[l][1] = TA(0);
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) acc[l][e] = TA(0);
             }
         }
         int c = 0;
-        for (; c + 4 <= nc; c += 4) {
-            TA v[4][PPT];
+        constexpr int UNR = 4;
+        for (; c + UNR <= nc; c += UNR) {
+            TV v[UNR][PPT];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const TV* vc = V + (long long)(c + u) * ldv;
-                v[u][0] = (TA)vc[p];
-                v[u][1] = full ? (TA)vc[p + 1] : TA(0);
-            }
+            for (int u = 0; u < UNR; ++u) load_pts<TV, PPT, true>(V + (long long)(c + u) * ldv + p, v[u]);
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < UNR; ++u)
 #pragma unroll
                 for (int l = 0; l < NOUT; ++l) {
-                    if (l < nout) {
-                        const TA m = (TA)M[(c + u) * nout + l];
-                        acc[l][0] = fma(v[u][0], m, acc[l][0]);
-                        acc[l][1] = fma(v[u][1], m, acc[l][1]);
-                    }
+                    const TA m = (TA)M[(c + u) * NOUT + l];
+#pragma unroll
+                    for (int e = 0; e < PPT; ++e) acc[l][e] = fma((TA)v[u][e], m, acc[l][e]);
                 }
         }
         for (; c < nc; ++c) {
-            const TV* vc = V + (long long)c * ldv;
-            const TA v0 = (TA)vc[p], v1 = full ? (TA)vc[p + 1] : TA(0);
+            TV v[PPT];
+            load_pts<TV, PPT, true>(V + (long long)c * ldv + p, v);
 #pragma unroll
             for (int l = 0; l < NOUT; ++l) {
-                if (l < nout) {
-                    const TA m = (TA)M[c * nout + l];
-                    acc[l][0] = fma(v0, m, acc[l][0]);
-                    acc[l][1] = fma(v1, m, acc[l][1]);
-                }
+                const TA m = (TA)M[c * NOUT + l];
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) acc[l][e] = fma((TA)v[e], m, acc[l][e]);
             }
         }
 #pragma unroll
         for (int l = 0; l < NOUT; ++l) {
-            if (l < nout) {
-                TO* oc = out + l * ldo;
-                oc[p] = (TO)acc[l][0];
-                if (full) oc[p + 1] = (TO)acc[l][1];
-            }
+            TO t[PPT];
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) t[e] = (TO)acc[l][e];
+            store_pts<TO, PPT>(out + l * ldo + p, t);
         }
         if (NORM) {
-            const double a0 = (double)acc[0][0], a1 = full ? (double)acc[0][1] : 0.0;
-            nrm = a0 * a0 + a1 * a1;
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) nrm += (double)acc[0][e] * (double)acc[0][e];
+        }
+    } else if (p < N) {  // ragged tail: element by element
+        for (long long q = p; q < N; ++q) {
+            TA acc[NOUT];
+#pragma unroll
+            for (int l = 0; l < NOUT; ++l) acc[l] = base ? (TA)base[l * ldb + q] : TA(0);
+            for (int c = 0; c < nc; ++c) {
+                const TA v = (TA)V[(long long)c * ldv + q];
+#pragma unroll
+                for (int l = 0; l < NOUT; ++l) acc[l] = fma(v, (TA)M[c * NOUT + l], acc[l]);
+            }
+#pragma unroll
+            for (int l = 0; l < NOUT; ++l) out[l * ldo + q] = (TO)acc[l];
+            if (NORM) nrm += (double)acc[0] * (double)acc[0];
         }
     }
     if (NORM) {
@@ -336,6 +389,19 @@ __global__ __launch_bounds__(kThreads) void k_update(
         block_sum<1>(v1, lds, o);
         if (threadIdx.x == 0) part[blockIdx.x] = o[0];
     }
+}
+
+// Squared norm partials of an FP64 vector (one value per workgroup).
+static __global__ __launch_bounds__(kThreads) void k_norm2(long long N, const double* __restrict__ v,
+                                                           double* __restrict__ part) {
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < N;
+         p += (long long)gridDim.x * kThreads)
+        s += v[p] * v[p];
+    double v1[1] = {s}, o[1];
+    block_sum<1>(v1, lds, o);
+    if (threadIdx.x == 0) part[blockIdx.x] = o[0];
 }
 
 }  // namespace sstep

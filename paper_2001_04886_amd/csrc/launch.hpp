@@ -12,6 +12,7 @@
 
 #include "../../include/sstep.h"
 #include "kernels.hpp"
+#include "mpk.hpp"
 
 namespace sstep {
 
@@ -243,28 +244,76 @@ inline void launch_level(Ctx& c, const StencilView& v, const T* in, const double
     c.end();
 }
 
-// Matrix powers of column 0 of Y into columns 1..s (kernel per level).
+template <typename T, int DIM, int L, int POS = (DIM == 3 ? 4 : 1)>
+inline void mpk_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
+                   const double* in_scale, const T* prev, const double* prev_scale,
+                   const MpkLevels& lv, const int* skip) {
+    constexpr int PX = MpkTile<DIM, POS>::PX, PY = MpkTile<DIM, POS>::PY;
+    constexpr int IX = PX - 2 * L, IY = (DIM == 3) ? PY - 2 * L : 1;
+    const int ntx = (v.nx + IX - 1) / IX;
+    const int nty = (DIM == 3) ? (v.ny + IY - 1) / IY : 1;
+    const int nmarch = (DIM == 3) ? v.nz : v.ny;
+    const long long tiles = (long long)ntx * nty;
+    const long long target = (DIM == 3) ? 2048 : 1024;
+    const long long nch = std::max<long long>(1, (target + tiles - 1) / tiles);
+    const int zchunk = (int)std::max<long long>((DIM == 3 ? 2 : 4) * L, (nmarch + nch - 1) / nch);
+    const int nzc = (nmarch + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL((k_mpk_fused<T, DIM, L, POS>), dim3((unsigned)(tiles * nzc)),
+                       dim3(MpkTile<DIM, POS>::THREADS), 0, c.st, v, out0, ldo, in, in_scale, prev,
+                       prev_scale, lv, ntx, nty, zchunk, skip);
+}
+
+// Matrix powers of column 0 of Y into columns 1..s: fused launches of at
+// most kMpkMaxL levels each.  Column 0 is read with in_scale applied.
 template <typename T>
 inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s, int basis,
                        const OpParams& P, const double* in_scale, const int* skip) {
     const double vb = (double)v.N * sizeof(T);
-    const double per_level = vb * (1.0 + s) / s;  // algorithmic: read 1, write s
-    for (int j = 1; j <= s; ++j) {
-        const T* yin = Y + (j - 1) * ldy;
-        const double* sc = (j == 1) ? in_scale : nullptr;
-        if (basis == SSTEP_BASIS_CHEBYSHEV) {
-            if (j == 1) {
-                launch_level<T>(c, v, yin, sc, nullptr, nullptr, 1.0 / P.cd, -P.cc / P.cd, 0.0,
-                                Y + j * ldy, skip, per_level);
+    int j0 = 0;
+    while (j0 < s) {
+        const int left = s - j0;
+        // 2-D: up to 8 levels per pass; 3-D: 2 levels per pass (deeper fusion
+        // of the 7-point stencil loses more to halo recomputation than it saves)
+        const int L = v.ndim == 3 ? std::min(left, 2)
+                                  : (left >= 8 ? 8 : (left >= 6 ? 6 : (left >= 4 ? 4 : left)));
+        MpkLevels lv;
+        for (int j = 0; j < L; ++j) {
+            const int lev = j0 + j + 1;  // global level index
+            if (basis == SSTEP_BASIS_CHEBYSHEV) {
+                lv.alpha[j] = (lev == 1 ? 1.0 : 2.0) / P.cd;
+                lv.beta[j] = -(lev == 1 ? 1.0 : 2.0) * P.cc / P.cd;
+                lv.gam[j] = lev == 1 ? 0.0 : -1.0;
             } else {
-                const double* psc = (j == 2) ? in_scale : nullptr;
-                launch_level<T>(c, v, yin, nullptr, Y + (j - 2) * ldy, psc, 2.0 / P.cd,
-                                -2.0 * P.cc / P.cd, -1.0, Y + j * ldy, skip, per_level);
+                lv.alpha[j] = 1.0 / P.sigma;
+                lv.beta[j] = 0.0;
+                lv.gam[j] = 0.0;
             }
-        } else {
-            launch_level<T>(c, v, yin, sc, nullptr, nullptr, 1.0 / P.sigma, 0.0, 0.0, Y + j * ldy,
-                            skip, per_level);
         }
+        const T* in = Y + (long long)j0 * ldy;
+        const double* isc = j0 == 0 ? in_scale : nullptr;
+        const T* prev = j0 >= 1 ? Y + (long long)(j0 - 1) * ldy : nullptr;
+        const double* psc = j0 == 1 ? in_scale : nullptr;
+        T* out0 = Y + (long long)(j0 + 1) * ldy;
+        // algorithmic bytes of the whole MPK call: read 1, write s
+        c.begin(SSTEP_K_MPK, vb * (L + (j0 == 0 ? 1.0 : 0.0)));
+#define SSTEP_MPK(D, LL) mpk_go<T, D, LL>(c, v, out0, ldy, in, isc, prev, psc, lv, skip)
+        if (v.ndim == 3) {
+            if (L == 2) mpk_go<T, 3, 2, 2>(c, v, out0, ldy, in, isc, prev, psc, lv, skip);
+            else mpk_go<T, 3, 1, 1>(c, v, out0, ldy, in, isc, prev, psc, lv, skip);
+        } else {
+            switch (L) {
+                case 8: SSTEP_MPK(2, 8); break;
+                case 6: SSTEP_MPK(2, 6); break;
+                case 4: SSTEP_MPK(2, 4); break;
+                case 3: SSTEP_MPK(2, 3); break;
+                case 2: SSTEP_MPK(2, 2); break;
+                default: SSTEP_MPK(2, 1); break;
+            }
+        }
+#undef SSTEP_MPK
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+        j0 += L;
     }
 }
 
@@ -311,9 +360,10 @@ template <typename T, int CA, int KZ>
 inline void gram_go(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
                     int nz1, const T* Z2, long long ldz2, int nz2, long long N, long long chunk,
                     int nct, int nchunk, double* part, const int* skip) {
-    hipLaunchKernelGGL((k_gram_partial<T, CA, KZ>), dim3((unsigned)(nct * nchunk)), dim3(kThreads),
-                       0, c.st, X, ldx, ncx, Z1, ldz1, nz1, Z2, ldz2, nz2, N, chunk, nct, part,
-                       skip);
+    constexpr int PPT = 16 / sizeof(T);
+    hipLaunchKernelGGL((k_gram_partial<T, CA, KZ, PPT>), dim3((unsigned)(nct * nchunk)),
+                       dim3(kThreads), 0, c.st, X, ldx, ncx, Z1, ldz1, nz1, Z2, ldz2, nz2, N, chunk,
+                       nct, part, skip);
 }
 
 // G (ncx x (nz1+nz2), row-major) = X^T [Z1 | Z2]
@@ -325,7 +375,9 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
     int KZ, CA, nct, nchunk;
     long long chunk;
     gram_geometry(N, ncx, nz, &KZ, &CA, &nct, &nchunk, &chunk);
-    c.begin(SSTEP_K_GRAM, (double)N * sizeof(T) * (ncx + nz));
+    // algorithmic bytes: every distinct column read once
+    const int ncols = (Z1 == X && ldz1 == ldx) ? std::max(ncx, nz1) + nz2 : ncx + nz;
+    c.begin(SSTEP_K_GRAM, (double)N * sizeof(T) * ncols);
     if (!Z2) Z2 = Z1;
 #define SSTEP_GRAM_CASE(K)                                                                      \
     case K:                                                                                     \
@@ -350,32 +402,57 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
     c.end();
     c.begin(SSTEP_K_GRAM, 0.0);
     const int nout = ncx * nz;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((nout + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       c.st, part, nchunk, ncx, KZ, nz, G, skip);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(kThreads), 0, c.st, part, nchunk,
+                       ncx, KZ, nz, G, skip);
     SSTEP_HIP(hipGetLastError());
     c.end();
 }
 
+// points per thread of the update kernel for a type combination
+template <typename TV, typename TB, typename TO>
+constexpr int update_ppt() {
+    constexpr int PA = 16 / sizeof(TV), PB = 16 / sizeof(TB), PO = 16 / sizeof(TO);
+    return PA > PB ? (PA > PO ? PA : PO) : (PB > PO ? PB : PO);
+}
+template <typename TV, typename TB, typename TO>
+inline long long update_blocks_t(long long N) {
+    const long long per = (long long)kThreads * update_ppt<TV, TB, TO>();
+    return (N + per - 1) / per;
+}
+// upper bound over all type combinations (sizing of norm partials)
 inline long long update_blocks(long long N) { return (N + 2 * kThreads - 1) / (2 * kThreads); }
 
-// out[:, l] = base[:, l] + sum_c V[:, c] M[c*nout + l]
+// out[:, l] = base[:, l] + sum_c V[:, c] M[c*nout + l], nout = 1..16
 template <typename TV, typename TB, typename TO, typename TA, bool NORM>
 inline void launch_update(Ctx& c, long long N, const TB* base, long long ldb, const TV* V,
                           long long ldv, int n2, const int* n2_dev, const double* M, TO* out,
                           long long ldo, int nout, double* part, const int* skip, double bytes,
                           int cls = SSTEP_K_UPDATE) {
     c.begin(cls, bytes);
-    const dim3 g((unsigned)update_blocks(N));
+    const dim3 g((unsigned)update_blocks_t<TV, TB, TO>(N));
 #define SSTEP_UPD(K)                                                                          \
-    hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM>), g, dim3(kThreads), 0, c.st, N, base, \
-                       ldb, V, ldv, n2, n2_dev, M, out, ldo, nout, part, skip)
-    if (nout <= 1) SSTEP_UPD(1);
-    else if (nout <= 2) SSTEP_UPD(2);
-    else if (nout <= 4) SSTEP_UPD(4);
-    else if (nout <= 8) SSTEP_UPD(8);
-    else if (nout <= 12) SSTEP_UPD(12);
-    else SSTEP_UPD(16);
+    case K:                                                                                   \
+        hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM && (K == 1)>), g, dim3(kThreads), \
+                           0, c.st, N, base, ldb, V, ldv, n2, n2_dev, M, out, ldo, part, skip); \
+        break;
+    switch (nout) {
+        SSTEP_UPD(1) SSTEP_UPD(2) SSTEP_UPD(3) SSTEP_UPD(4) SSTEP_UPD(5) SSTEP_UPD(6)
+        SSTEP_UPD(7) SSTEP_UPD(8) SSTEP_UPD(9) SSTEP_UPD(10) SSTEP_UPD(11) SSTEP_UPD(12)
+        SSTEP_UPD(13) SSTEP_UPD(14) SSTEP_UPD(15) SSTEP_UPD(16)
+        default:
+            throw HipFailure{hipErrorInvalidValue, "update width"};
+    }
 #undef SSTEP_UPD
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+inline int norm_blocks(long long N) {
+    return (int)std::min<long long>(1024, (N + kThreads - 1) / kThreads);
+}
+inline void launch_norm2(Ctx& c, long long N, const double* v, double* part) {
+    c.begin(SSTEP_K_SCALAR, 8.0 * N);
+    hipLaunchKernelGGL(k_norm2, dim3(norm_blocks(N)), dim3(kThreads), 0, c.st, N, v, part);
     SSTEP_HIP(hipGetLastError());
     c.end();
 }

@@ -198,7 +198,7 @@ static OmLayout om_layout(const sstep_stencil& A, int s, int k) {
     size_t gp = gram_partial_doubles(L.N, s, s + 1);
     for (int nf = 1; nf <= k; ++nf) gp = std::max(gp, gram_partial_doubles(L.N, nf * s, s + 1));
     L.off_gpart = take(sizeof(double) * gp);
-    L.off_npart = take(sizeof(double) * (size_t)update_blocks(L.N));
+    L.off_npart = take(sizeof(double) * (size_t)std::max<long long>(update_blocks(L.N), norm_blocks(L.N)));
     L.off_rpart = take(sizeof(double) * (size_t)stencil_blocks(make_view(A)));
     L.off_scratch = take(sizeof(double) * 64 * 3);
     L.total = off;
@@ -251,7 +251,7 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
     SSTEP_HIP(hipMemcpyAsync(dst, &h, sizeof(OmState), hipMemcpyHostToDevice, c.st));
 
     const double vb = 8.0 * N;
-    const int nrpart = (int)stencil_blocks(v), nnpart = (int)update_blocks(N);
+    const int nrpart = (int)stencil_blocks(v), nnpart = (int)update_blocks_t<double, double, double>(N);
     auto scalar = [&](auto kern, int threads, auto... args) {
         c.begin(SSTEP_K_SCALAR, 0.0);
         hipLaunchKernelGGL(kern, dim3(1), dim3(threads), 0, c.st, a, args...);
@@ -260,10 +260,8 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
     };
     c.cur_block = -1;
     // ||f||
-    launch_update<double, double, double, double, true>(c, N, f, 0, (const double*)nullptr, 0, 0,
-                                                        nullptr, nullptr, Y, ld, 1, npart, nullptr,
-                                                        2 * vb, SSTEP_K_SCALAR);
-    scalar(k_om_init, kThreads, (const double*)npart, nnpart);
+    launch_norm2(c, N, f, npart);
+    scalar(k_om_init, kThreads, (const double*)npart, norm_blocks(N));
     auto true_residual = [&]() {
         c.cur_block = -1;
         launch_residual<double>(c, v, f, x, Y, rpart);
