@@ -39,6 +39,26 @@ def vec_passes_gmres(blocks_per_cycle, s):
     return tot
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2001_04886_amd", "csrc", "kernels.hpp")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of the kernel class from the committed rocprofv3
+    counter summary, or None when the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "sgmres_256cube_s8m40_fp64_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hash") != kernel_source_hash() or kind not in rec:
+        return None
+    return rec[kind]["hbm_bytes_per_launch"]
+
+
 def blocks_per_cycle(total_blocks, cycles, m):
     out = []
     left = total_blocks
@@ -62,6 +82,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the GMRES(ms) comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-blocks", type=int, default=2)
+    ap.add_argument("--workload", choices=["gmres3d", "mixed3d", "omin2d", "small2d"],
+                    default="gmres3d")
+    ap.add_argument("--omin-iters", type=int, default=200)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -77,6 +100,8 @@ def main():
 
     S.load()
     dev = torch.device("cuda:0")
+    if args.workload != "gmres3d":
+        return OTHER[args.workload](args)
     prob = PB.cube_3d(args.n, seed=0, gamma=50.0)
     A = S.Stencil.from_problem(prob)
     N = prob.N
@@ -125,6 +150,7 @@ def main():
                       "bytes": by / args.steps}
     dom = max(("gram", "update", "mpk"), key=lambda k: classes[k]["ms"])
     dom_gbs = classes[dom]["GBs"] or 0.0
+    traffic = measured_traffic(dom)
     total_bytes = sum(classes[k]["bytes"] for k in classes)
     out = {
         "metric": "s-step GMRES time to 1e-8 rel. resid + HBM GB/s, 7-pt 256^3, vs plain",
@@ -151,7 +177,9 @@ def main():
         "algorithmic_GBs_solve": total_bytes / (ms_per_step * 1e-3) / 1e9,
         "kernels": classes,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
+                     "algorithmic_bytes_per_launch": classes[dom]["bytes"] / max(classes[dom]["launches"], 1)},
     }
 
     if not args.no_plain:
@@ -192,6 +220,152 @@ def main():
         print(f"# cpu oracle sample: {tc1 - tc0:.1f} s for {args.cpu_blocks} blocks", file=sys.stderr,
               flush=True)
     print(json.dumps(out), flush=True)
+
+
+def _classes(S, infos, steps):
+    out = {}
+    for k in S.KERNEL_CLASSES:
+        ms = sum(i.ms[k] for i in infos)
+        by = sum(i.bytes[k] for i in infos)
+        out[k] = {"ms": ms / steps, "launches": sum(i.launches[k] for i in infos) // steps,
+                  "GBs": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None,
+                  "bytes": by / steps}
+    return out
+
+
+def _line(metric, value, unit, hib, ms, args, dtype, workload, extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": hib, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": workload}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed3d(args):
+    """FP32 basis / FP64 Gram, least squares and refinement on the 256^3
+    problem, s in {4, 8, 12}, tol 1e-10, against FP64 s-step GMRES."""
+    import torch
+    from paper_2001_04886_amd import problems as PB
+    from paper_2001_04886_amd import sstep as S
+    dev = torch.device("cuda:0")
+    prob = PB.cube_3d(args.n, seed=0, gamma=50.0)
+    A = S.Stencil.from_problem(prob)
+    xt = torch.from_numpy(prob.x_true()).to(dev)
+    f = torch.empty_like(xt)
+    S.stencil_apply(A, xt, f)
+    tol = 1e-10
+    wsb = max(S.workspace_bytes(A, S.METHOD_GMRES, 8, args.m),
+              S.workspace_bytes(A, S.METHOD_GMRES, 12, args.m, S.MIXED))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    x = torch.zeros_like(xt)
+    res = {}
+    for name, s, prec, basis in [("fp64_s8", 8, S.FP64, S.MONOMIAL), ("mixed_s4", 4, S.MIXED, S.MONOMIAL),
+                                 ("mixed_s8", 8, S.MIXED, S.MONOMIAL),
+                                 ("mixed_s12", 12, S.MIXED, S.CHEBYSHEV)]:
+        infos = []
+        for rep in range(args.warmup + args.steps):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = S.gmres_solve(A, f, x, s, args.m, tol, precision=prec, basis=basis, workspace=ws,
+                                 profile=True)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                infos.append((time.perf_counter() - t0, info))
+        t = sum(a for a, _ in infos) / len(infos)
+        info = infos[-1][1]
+        xerr = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+        res[name] = {"s": t, "blocks": info.iters, "cycles": info.cycles, "status": info.status,
+                     "rel_resid": info.rel_resid, "x_err_vs_true": xerr,
+                     "basis": "chebyshev" if basis == S.CHEBYSHEV else "monomial",
+                     "kernels": _classes(S, [i for _, i in infos], len(infos))}
+        print(f"# {name}: {t:.3f} s blocks={info.iters} cycles={info.cycles} rel_resid={info.rel_resid:.2e}"
+              f" x_err={xerr:.2e}", file=sys.stderr, flush=True)
+    v = res["mixed_s8"]["s"]
+    upd = res["mixed_s8"]["kernels"]["update"]["GBs"] or 0.0
+    _line("mixed-precision s-step GMRES time to 1e-10 rel. resid, 7-pt 256^3", v, "s", False, v * 1e3,
+          args, "f32+f64",
+          f"3-D 7-pt convection-diffusion {args.n}^3 gamma=50, s-step GMRES(m={args.m}), FP32 basis, "
+          f"FP64 Gram/LS/refinement, tol 1e-10 (s=8 headline; s=4, 12 and FP64 s=8 alongside)",
+          {"results": res, "speedup_vs_fp64": res["fp64_s8"]["s"] / v,
+           "roofline": {"bound": "hbm", "kernel": "update", "achieved": upd, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": upd / HBM_PEAK_GBS, "traffic": None}})
+
+
+def bench_omin2d(args):
+    """s-step Orthomin(k=8, s=8) on the 2-D 4096^2 problem, gamma = 50."""
+    import torch
+    from paper_2001_04886_amd import problems as PB
+    from paper_2001_04886_amd import sstep as S
+    dev = torch.device("cuda:0")
+    n = 4096 if args.n == 256 else args.n
+    prob = PB.square_2d_large(n, seed=0, gamma=50.0)
+    A = S.Stencil.from_problem(prob)
+    xt = torch.from_numpy(prob.x_true()).to(dev)
+    f = torch.empty_like(xt)
+    S.stencil_apply(A, xt, f)
+    ws = S.allocate_workspace(A, S.METHOD_OMIN, 8, 8)
+    x = torch.zeros_like(xt)
+    infos = []
+    for rep in range(args.warmup + args.steps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = S.omin_solve(A, f, x, 8, 8, 1e-8, max_iters=args.omin_iters, workspace=ws, profile=True)
+        torch.cuda.synchronize()
+        if rep >= args.warmup:
+            infos.append((time.perf_counter() - t0, info))
+        print(f"# omin rep {rep}: {time.perf_counter() - t0:.2f} s iters={info.iters} "
+              f"rel_resid={info.rel_resid:.2e} status={info.status}", file=sys.stderr, flush=True)
+    t = sum(a for a, _ in infos) / len(infos)
+    info = infos[-1][1]
+    cls = _classes(S, [i for _, i in infos], len(infos))
+    dom = max(("gram", "update", "mpk"), key=lambda k: cls[k]["ms"])
+    g = cls[dom]["GBs"] or 0.0
+    per_it = t * 1e3 / max(info.iters, 1)
+    _line("s-step Omin(k=8,s=8) time per s-step iteration, 5-pt 4096^2", per_it, "ms/iter", False,
+          t * 1e3, args, "f64",
+          f"2-D 5-pt convection-diffusion {n}^2 gamma=50, s-step Orthomin(k=8, s=8), FP64, "
+          f"{args.omin_iters} iterations (tol 1e-8 not reached within the cap)",
+          {"iters": info.iters, "status": info.status, "rel_resid": info.rel_resid,
+           "solve_s": t, "kernels": cls,
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": g, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": g / HBM_PEAK_GBS, "traffic": None}})
+
+
+def bench_small2d(args):
+    """64 x 64, gamma = 10: s-GMRES(m=20, s=4) and s-Omin(k=4, s=4) to 1e-8."""
+    import torch
+    from paper_2001_04886_amd import problems as PB
+    from paper_2001_04886_amd import sstep as S
+    dev = torch.device("cuda:0")
+    prob = PB.small_2d(0)
+    A = S.Stencil.from_problem(prob)
+    xt = torch.from_numpy(prob.x_true()).to(dev)
+    f = torch.empty_like(xt)
+    S.stencil_apply(A, xt, f)
+    out = {}
+    for name, fn, km in [("gmres", S.gmres_solve, 20), ("omin", S.omin_solve, 4)]:
+        ws = S.allocate_workspace(A, S.METHOD_GMRES if name == "gmres" else S.METHOD_OMIN, 4, km)
+        x = torch.zeros_like(xt)
+        ts = []
+        for rep in range(args.warmup + max(args.steps, 5)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = fn(A, f, x, 4, km, 1e-8, workspace=ws)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                ts.append(time.perf_counter() - t0)
+        out[name] = {"ms": 1e3 * sorted(ts)[len(ts) // 2], "iters": info.iters,
+                     "rel_resid": info.rel_resid, "status": info.status}
+    _line("s-step GMRES(20,4) time to 1e-8, 5-pt 64^2", out["gmres"]["ms"] / 1e3, "s", False,
+          out["gmres"]["ms"], args, "f64", "2-D 5-pt convection-diffusion 64^2 gamma=10, "
+          "s-GMRES(m=20, s=4) and s-Omin(k=4, s=4), FP64, tol 1e-8 (latency bound)", {"results": out})
+
+
+OTHER = {"mixed3d": bench_mixed3d, "omin2d": bench_omin2d, "small2d": bench_small2d}
 
 
 if __name__ == "__main__":

@@ -87,12 +87,14 @@ typedef struct {
 
 /* kernel classes reported in sstep_info (index into the arrays below) */
 enum {
-    SSTEP_K_MPK = 0,      /* matrix powers                     */
-    SSTEP_K_GRAM = 1,     /* block Gram (all inner products)   */
-    SSTEP_K_UPDATE = 2,   /* block updates / assembly          */
-    SSTEP_K_RESID = 3,    /* true residual r = f - A x         */
-    SSTEP_K_SCALAR = 4,   /* small FP64 solves and reductions  */
-    SSTEP_K_NCLASS = 5
+    SSTEP_K_MPK = 0,      /* matrix powers                                            */
+    SSTEP_K_GRAM = 1,     /* block Gram against the stored blocks (partial + reduce)  */
+    SSTEP_K_UPDATE = 2,   /* block update against the stored blocks                   */
+    SSTEP_K_RESID = 3,    /* true residual r = f - A x                                */
+    SSTEP_K_SCALAR = 4,   /* small FP64 solves                                        */
+    SSTEP_K_VEC = 5,      /* short vector passes: block self-Gram, next start vector,
+                             solution assembly, x / r updates, norms                  */
+    SSTEP_K_NCLASS = 6
 };
 
 typedef struct {

@@ -541,14 +541,14 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
                                                  vb * (ncx + 2 * s));
             }
             launch_gram<T>(c, Yk, ld, s + 1, Yk, ld, s + 1, (const T*)nullptr, 0, 0, N, gpart,
-                           a.Gout, done);
+                           a.Gout, done, SSTEP_K_VEC);
             c.begin(SSTEP_K_SCALAR, 0.0);
             hipLaunchKernelGGL(k_gm_block, dim3(1), dim3(64), 0, c.st, a);
             SSTEP_HIP(hipGetLastError());
             c.end();
             launch_update<T, T, T, T, true>(c, N, Yk + (long long)s * ld, ld, Yk, ld, s, nullptr,
                                             dst->coefN4b, Yk + (long long)s * ld, ld, 1, npart,
-                                            &dst->skip_n4b, vb * (s + 2));
+                                            &dst->skip_n4b, vb * (s + 2), SSTEP_K_VEC);
             c.begin(SSTEP_K_SCALAR, 0.0);
             hipLaunchKernelGGL(k_gm_nu, dim3(1), dim3(kThreads), 0, c.st, a, npart, nnpart);
             hipLaunchKernelGGL(k_gm_hess_cols, dim3(kb + 1), dim3(kThreads), 0, c.st, a);
@@ -564,7 +564,7 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
         // x = x0 + V y (eq. (8)); column count read on the device
         launch_update<T, double, double, double, false>(c, N, x, 0, basis, ld, K, &dst->ncols,
                                                         a.coefA, x, 0, 1, nullptr, &dst->skip_asm,
-                                                        0.0);
+                                                        0.0, SSTEP_K_VEC);
         residual_and_start();
         const int before = ret.blocks_total;
         read_state();

@@ -183,14 +183,17 @@ __device__ __forceinline__ void store_pts(T* __restrict__ p, const T (&v)[PPT]) 
 // Z = [Z1 (nz1 columns) | Z2 (nz2 columns)], nz1 + nz2 <= KZ.  Accumulation
 // in FP64.  The workgroups of one chunk are consecutive on one XCD, so Z is
 // read from HBM once and then served by that XCD's L2; X is streamed with
-// non-temporal loads.  PPT points per thread per step.
+// non-temporal loads.  The loop is software-pipelined: the loads of the next
+// step are in flight while the FMAs of the current step run.
 // ---------------------------------------------------------------------------
-template <typename T, int CA, int KZ, int PPT>
+template <typename T, int CA, int KZ>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(
     const T* __restrict__ X, long long ldx, int ncx, const T* __restrict__ Z1, long long ldz1,
     int nz1, const T* __restrict__ Z2, long long ldz2, int nz2, long long N, long long chunk,
     int nct, double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
+    constexpr int PPT = 16 / sizeof(T);  // points per thread per step (one 16-byte load)
+    constexpr int STEP = PPT * kThreads;
     __shared__ double lds[4 * CA * KZ];
     const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = b % nct;
@@ -204,56 +207,61 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(
     for (int a = 0; a < CA; ++a)
 #pragma unroll
         for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = 0.0;
-
+    // columns beyond ncx / nz alias valid ones; their sums are discarded
     const T* zc[KZ];
 #pragma unroll
-    for (int jz = 0; jz < KZ; ++jz)
-        zc[jz] = jz < nz1 ? Z1 + jz * ldz1 : (jz < nz ? Z2 + (jz - nz1) * ldz2 : Z1);
+    for (int jz = 0; jz < KZ; ++jz) {
+        const int j = jz < nz ? jz : nz - 1;
+        zc[jz] = j < nz1 ? Z1 + j * ldz1 : Z2 + (j - nz1) * ldz2;
+    }
     const T* xc[CA];
 #pragma unroll
-    for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : c0) * ldx;
+    for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : ncx - 1) * ldx;
 
-    // full vectors: chunk starts are multiples of 512 points
+    // full vectors (chunk starts are multiples of 512 points)
     const long long pv1 = p0 + (p1 - p0) / PPT * PPT;
-    for (long long p = p0 + (long long)PPT * threadIdx.x; p < pv1; p += (long long)PPT * kThreads) {
-        double zv[KZ][PPT];
+    long long p = p0 + (long long)PPT * threadIdx.x;
+    T zn[KZ][PPT], xn[CA][PPT];
+    if (p < pv1) {
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) {
-            if (jz < nz) {
-                T t[PPT];
-                load_pts<T, PPT, false>(zc[jz] + p, t);
+        for (int jz = 0; jz < KZ; ++jz) load_pts<T, PPT, false>(zc[jz] + p, zn[jz]);
 #pragma unroll
-                for (int e = 0; e < PPT; ++e) zv[jz][e] = (double)t[e];
-            } else {
-#pragma unroll
-                for (int e = 0; e < PPT; ++e) zv[jz][e] = 0.0;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < CA; ++a) {
-            if (c0 + a < ncx) {
-                T t[PPT];
-                load_pts<T, PPT, true>(xc[a] + p, t);
-#pragma unroll
-                for (int e = 0; e < PPT; ++e) {
-                    const double xv = (double)t[e];
-#pragma unroll
-                    for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(xv, zv[jz][e], acc[a][jz]);
-                }
-            }
-        }
+        for (int a = 0; a < CA; ++a) load_pts<T, PPT, true>(xc[a] + p, xn[a]);
     }
-    for (long long p = pv1 + threadIdx.x; p < p1; p += kThreads) {  // ragged tail
+    for (; p < pv1; p += STEP) {
+        T zv[KZ][PPT], xv[CA][PPT];
+#pragma unroll
+        for (int jz = 0; jz < KZ; ++jz)
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) zv[jz][e] = zn[jz][e];
+#pragma unroll
+        for (int a = 0; a < CA; ++a)
+#pragma unroll
+            for (int e = 0; e < PPT; ++e) xv[a][e] = xn[a][e];
+        const long long pn = p + STEP;
+        if (pn < pv1) {
+#pragma unroll
+            for (int jz = 0; jz < KZ; ++jz) load_pts<T, PPT, false>(zc[jz] + pn, zn[jz]);
+#pragma unroll
+            for (int a = 0; a < CA; ++a) load_pts<T, PPT, true>(xc[a] + pn, xn[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < CA; ++a)
+#pragma unroll
+            for (int jz = 0; jz < KZ; ++jz)
+#pragma unroll
+                for (int e = 0; e < PPT; ++e)
+                    acc[a][jz] = fma((double)xv[a][e], (double)zv[jz][e], acc[a][jz]);
+    }
+    for (long long q = pv1 + threadIdx.x; q < p1; q += kThreads) {  // ragged tail
         double z0[KZ];
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) z0[jz] = jz < nz ? to_f64(zc[jz][p]) : 0.0;
+        for (int jz = 0; jz < KZ; ++jz) z0[jz] = to_f64(zc[jz][q]);
 #pragma unroll
         for (int a = 0; a < CA; ++a) {
-            if (c0 + a < ncx) {
-                const double x0 = to_f64(xc[a][p]);
+            const double x0 = to_f64(xc[a][q]);
 #pragma unroll
-                for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
-            }
+            for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
         }
     }
     double flat[CA * KZ], outv[CA * KZ];
@@ -334,10 +342,23 @@ __global__ __launch_bounds__(kThreads) void k_update(
         }
         int c = 0;
         constexpr int UNR = 4;
+        // software pipeline: the next UNR columns load while this batch's FMAs run
+        TV vn[UNR][PPT];
+        if (UNR <= nc) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) load_pts<TV, PPT, true>(V + (long long)u * ldv + p, vn[u]);
+        }
         for (; c + UNR <= nc; c += UNR) {
             TV v[UNR][PPT];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) load_pts<TV, PPT, true>(V + (long long)(c + u) * ldv + p, v[u]);
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int e = 0; e < PPT; ++e) v[u][e] = vn[u][e];
+            if (c + 2 * UNR <= nc) {
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    load_pts<TV, PPT, true>(V + (long long)(c + UNR + u) * ldv + p, vn[u]);
+            }
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
 #pragma unroll

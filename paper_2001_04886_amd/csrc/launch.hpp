@@ -329,7 +329,7 @@ inline void launch_residual(Ctx& c, const StencilView& v, const double* f, const
 }
 
 // Gram geometry: column-tile width for a given Z width, and the point chunk.
-constexpr int gram_ca_c(int kz) { return kz <= 2 ? 8 : (kz <= 9 ? 4 : 2); }
+constexpr int gram_ca_c(int kz) { return kz <= 9 ? 8 : 4; }
 inline int gram_ca(int kz) { return gram_ca_c(kz); }
 inline int gram_kz(int nz) {
     static const int ks[] = {1, 2, 4, 8, 9, 12, 13, 16, 17};
@@ -342,7 +342,7 @@ inline void gram_geometry(long long N, int ncx, int nz, int* KZ, int* CA, int* n
     *KZ = gram_kz(nz);
     *CA = gram_ca(*KZ);
     *nct = (ncx + *CA - 1) / *CA;
-    long long nch = std::min<long long>((N + 8191) / 8192, std::max(1, 4096 / *nct));
+    long long nch = std::min<long long>((N + 8191) / 8192, std::max(1, 2048 / *nct));
     nch = std::max<long long>(1, std::min<long long>(nch, 512));
     long long ck = round_up((N + nch - 1) / nch, 512);
     nch = (N + ck - 1) / ck;
@@ -360,8 +360,7 @@ template <typename T, int CA, int KZ>
 inline void gram_go(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
                     int nz1, const T* Z2, long long ldz2, int nz2, long long N, long long chunk,
                     int nct, int nchunk, double* part, const int* skip) {
-    constexpr int PPT = 16 / sizeof(T);
-    hipLaunchKernelGGL((k_gram_partial<T, CA, KZ, PPT>), dim3((unsigned)(nct * nchunk)),
+    hipLaunchKernelGGL((k_gram_partial<T, CA, KZ>), dim3((unsigned)(nct * nchunk)),
                        dim3(kThreads), 0, c.st, X, ldx, ncx, Z1, ldz1, nz1, Z2, ldz2, nz2, N, chunk,
                        nct, part, skip);
 }
@@ -370,14 +369,14 @@ inline void gram_go(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, lon
 template <typename T>
 inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
                         int nz1, const T* Z2, long long ldz2, int nz2, long long N, double* part,
-                        double* G, const int* skip) {
+                        double* G, const int* skip, int cls = SSTEP_K_GRAM) {
     const int nz = nz1 + nz2;
     int KZ, CA, nct, nchunk;
     long long chunk;
     gram_geometry(N, ncx, nz, &KZ, &CA, &nct, &nchunk, &chunk);
     // algorithmic bytes: every distinct column read once
     const int ncols = (Z1 == X && ldz1 == ldx) ? std::max(ncx, nz1) + nz2 : ncx + nz;
-    c.begin(SSTEP_K_GRAM, (double)N * sizeof(T) * ncols);
+    c.begin(cls, (double)N * sizeof(T) * ncols);  // one record: partial + reduce
     if (!Z2) Z2 = Z1;
 #define SSTEP_GRAM_CASE(K)                                                                      \
     case K:                                                                                     \
@@ -399,8 +398,6 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
     }
 #undef SSTEP_GRAM_CASE
     SSTEP_HIP(hipGetLastError());
-    c.end();
-    c.begin(SSTEP_K_GRAM, 0.0);
     const int nout = ncx * nz;
     hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(kThreads), 0, c.st, part, nchunk,
                        ncx, KZ, nz, G, skip);
@@ -451,7 +448,7 @@ inline int norm_blocks(long long N) {
     return (int)std::min<long long>(1024, (N + kThreads - 1) / kThreads);
 }
 inline void launch_norm2(Ctx& c, long long N, const double* v, double* part) {
-    c.begin(SSTEP_K_SCALAR, 8.0 * N);
+    c.begin(SSTEP_K_VEC, 8.0 * N);
     hipLaunchKernelGGL(k_norm2, dim3(norm_blocks(N)), dim3(kThreads), 0, c.st, N, v, part);
     SSTEP_HIP(hipGetLastError());
     c.end();

@@ -308,14 +308,15 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
                 const int nfill = std::min(i + 1, k);
                 double* APi = APr + (long long)slot * s * ld;
                 double* Pi = Pr + (long long)slot * s * ld;
-                launch_gram<double>(c, APi, ld, s, APi, ld, s, Y, ld, 1, N, gpart, a.Gout, done);
+                launch_gram<double>(c, APi, ld, s, APi, ld, s, Y, ld, 1, N, gpart, a.Gout, done,
+                                    SSTEP_K_VEC);
                 scalar(k_om_step1, 64, slot);
                 launch_update<double, double, double, double, false>(
                     c, N, x, 0, Pi, ld, s, nullptr, dst->coef_x, x, 0, 1, nullptr, done,
-                    (s + 2) * vb);
+                    (s + 2) * vb, SSTEP_K_VEC);
                 launch_update<double, double, double, double, true>(
                     c, N, Y, 0, APi, ld, s, nullptr, dst->coef_r, Y, 0, 1, npart, done,
-                    (s + 2) * vb);
+                    (s + 2) * vb, SSTEP_K_VEC);
                 scalar(k_om_check, kThreads, (const double*)npart, nnpart);
                 launch_mpk<double>(c, v, Y, ld, s, opt.basis, P, nullptr, done);
                 launch_gram<double>(c, APr, ld, nfill * s, Y, ld, s + 1, (const double*)nullptr, 0,

@@ -20,8 +20,8 @@ OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = 0
 MONOMIAL, CHEBYSHEV = 0, 1
 FP64, MIXED = 0, 1
 METHOD_OMIN, METHOD_GMRES = 0, 1
-K_MPK, K_GRAM, K_UPDATE, K_RESID, K_SCALAR, K_NCLASS = 0, 1, 2, 3, 4, 5
-KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar")
+K_MPK, K_GRAM, K_UPDATE, K_RESID, K_SCALAR, K_VEC, K_NCLASS = 0, 1, 2, 3, 4, 5, 6
+KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar", "vec")
 
 # every symbol declared in include/sstep.h
 EXPORTS = (
