@@ -83,6 +83,12 @@ typedef struct {
                              at least sstep_workspace_bytes(); NULL = allocated per call  */
     size_t workspace_bytes;
     void *stream;         /* hipStream_t                                                   */
+    /* batched solver only (sstep_batch_plan_create): launch shape of the
+       persistent kernel; 0 = defaults (512 threads, 1 workgroup per CU) */
+    int32_t batch_threads;     /* 256, 512 or 1024 threads per workgroup               */
+    int32_t batch_wgs_per_cu;  /* resident workgroups per compute unit (1..4)          */
+    int32_t batch_graph;       /* 1: capture the launch in a hipGraph, replay it       */
+    int32_t reserved;
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */
@@ -153,6 +159,47 @@ int sstep_gmres_solve(const sstep_stencil *A, const double *f, double *x, int s,
  * precision must be SSTEP_FP64. */
 int sstep_omin_solve(const sstep_stencil *A, const double *f, double *x, int s, int k,
                      double tol, const sstep_options *opt, sstep_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* Batched s-step GMRES: many independent systems in one persistent launch */
+/* ---------------------------------------------------------------------- */
+
+/* Opaque plan: system table on the device, per-system basis workspace and
+ * (with opt->batch_graph) the captured hipGraph of the launch. */
+typedef struct sstep_batch_plan_s *sstep_batch_plan;
+
+/* Device workspace (bytes) of a batch plan (sum of the systems' bases plus
+ * per-workgroup dense state). */
+size_t sstep_batch_workspace_bytes(int nsys, const sstep_stencil *A, int s, int m,
+                                   const sstep_options *opt);
+
+/* Create a plan for nsys independent systems A[i] x[i] = f[i] (restarted
+ * s-step GMRES(m), Sec. 4, Alg. 4.2, FP64, monomial basis).
+ *   A    : HOST array [nsys] of constant-coefficient stencils (coef == NULL)
+ *   f, x : HOST arrays [nsys] of DEVICE pointers (x: initial guess in, solution
+ *          out at every execution; the pointers must stay valid for the plan)
+ *   s    : 1..8;  m: s-blocks per cycle, m <= 128 and m*s <= 512
+ * One persistent kernel of (compute units x batch_wgs_per_cu) workgroups;
+ * each workgroup takes systems from a queue (largest first) and runs a whole
+ * solve with workgroup-local synchronisation only.  Returns SSTEP_OK or an
+ * error; *plan is NULL on error. */
+int sstep_batch_plan_create(sstep_batch_plan *plan, int nsys, const sstep_stencil *A,
+                            const double *const *f, double *const *x, int s, int m, double tol,
+                            const sstep_options *opt);
+
+/* Run the plan once (replays the graph when captured) and wait.  info: HOST
+ * array [nsys] or NULL; ms_total of every entry is the batch wall time.
+ * Returns SSTEP_OK if every system converged, SSTEP_NOT_CONVERGED if any hit
+ * the cap, or the first error. */
+int sstep_batch_plan_execute(sstep_batch_plan plan, sstep_info *info);
+
+/* Free the plan (and its workspace if the library allocated it). */
+void sstep_batch_plan_destroy(sstep_batch_plan plan);
+
+/* Convenience: create, execute once, destroy. */
+int sstep_gmres_solve_batched(int nsys, const sstep_stencil *A, const double *const *f,
+                              double *const *x, int s, int m, double tol,
+                              const sstep_options *opt, sstep_info *info);
 
 /* ---------------------------------------------------------------------- */
 /* Primitives (the building blocks of the solvers; enqueue only)           */

@@ -173,6 +173,71 @@ int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, 
     });
 }
 
+static int batch_args_ok(int nsys, const sstep_stencil* A, const double* const* f,
+                         double* const* x, int s, int m, double tol, const sstep_options* opt) {
+    if (nsys < 1 || !A || !f || !x || s < 1 || s > 8 || m < 1 || m > 128 || m * s > 512 ||
+        !(tol >= 0.0))
+        return 0;
+    if (opt) {
+        if (opt->precision != SSTEP_FP64 || opt->basis != SSTEP_BASIS_MONOMIAL ||
+            opt->max_iters < 0 || !(opt->sigma >= 0.0))
+            return 0;
+        if (opt->batch_threads != 0 && opt->batch_threads != 256 && opt->batch_threads != 512 &&
+            opt->batch_threads != 1024)
+            return 0;
+        if (opt->batch_wgs_per_cu < 0 || opt->batch_wgs_per_cu > 4) return 0;
+    }
+    for (int i = 0; i < nsys; ++i) {
+        if (!stencil_ok(&A[i]) || A[i].coef || !f[i] || !x[i]) return 0;
+        if (grid_points(A[i]) > (1LL << 30)) return 0;
+    }
+    return 1;
+}
+
+size_t sstep_batch_workspace_bytes(int nsys, const sstep_stencil* A, int s, int m,
+                                   const sstep_options* opt) {
+    if (nsys < 1 || !A || s < 1 || s > 8 || m < 1 || m > 128 || m * s > 512) return 0;
+    for (int i = 0; i < nsys; ++i)
+        if (!stencil_ok(&A[i])) return 0;
+    const int wpc = (opt && opt->batch_wgs_per_cu > 0) ? opt->batch_wgs_per_cu : 1;
+    return batched_workspace_bytes(nsys, A, s, m, batched_slots(nsys, wpc));
+}
+
+int sstep_batch_plan_create(sstep_batch_plan* plan, int nsys, const sstep_stencil* A,
+                            const double* const* f, double* const* x, int s, int m, double tol,
+                            const sstep_options* opt) {
+    if (!plan) return SSTEP_ERR_ARG;
+    *plan = nullptr;
+    if (!batch_args_ok(nsys, A, f, x, s, m, tol, opt)) return SSTEP_ERR_ARG;
+    sstep_options o;
+    if (opt) o = *opt;
+    else sstep_default_options(&o);
+    return guarded(nullptr, [&]() -> int {
+        void* p = nullptr;
+        const int st = batched_plan_create(&p, nsys, A, f, x, s, m, tol, o);
+        *plan = (sstep_batch_plan)p;
+        return st;
+    });
+}
+
+int sstep_batch_plan_execute(sstep_batch_plan plan, sstep_info* info) {
+    if (!plan) return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int { return batched_plan_execute(plan, info, nullptr); });
+}
+
+void sstep_batch_plan_destroy(sstep_batch_plan plan) { batched_plan_destroy(plan); }
+
+int sstep_gmres_solve_batched(int nsys, const sstep_stencil* A, const double* const* f,
+                              double* const* x, int s, int m, double tol,
+                              const sstep_options* opt, sstep_info* info) {
+    sstep_batch_plan plan = nullptr;
+    int st = sstep_batch_plan_create(&plan, nsys, A, f, x, s, m, tol, opt);
+    if (st != SSTEP_OK) return st;
+    st = sstep_batch_plan_execute(plan, info);
+    sstep_batch_plan_destroy(plan);
+    return st;
+}
+
 int sstep_stencil_apply(const sstep_stencil* A, const double* x, double* y, void* stream) {
     if (!stencil_ok(A) || !x || !y || x == y) return SSTEP_ERR_ARG;
     return guarded(nullptr, [&]() -> int {

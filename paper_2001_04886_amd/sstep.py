@@ -28,6 +28,8 @@ EXPORTS = (
     "sstep_default_options", "sstep_status_string", "sstep_workspace_bytes",
     "sstep_gmres_solve", "sstep_omin_solve", "sstep_stencil_apply",
     "sstep_kernel_mpk", "sstep_kernel_gram", "sstep_kernel_update",
+    "sstep_batch_workspace_bytes", "sstep_batch_plan_create", "sstep_batch_plan_execute",
+    "sstep_batch_plan_destroy", "sstep_gmres_solve_batched",
 )
 
 
@@ -40,7 +42,9 @@ class OptionsC(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("precision", C.c_int32), ("basis", C.c_int32),
                 ("profile", C.c_int32), ("sigma", C.c_double), ("inner_tol", C.c_double),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("batch_threads", C.c_int32),
+                ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -84,6 +88,18 @@ def load(path: str | None = None):
     lib.sstep_kernel_gram.restype = i32
     lib.sstep_kernel_update.argtypes = [vp, i64, i32, vp, i64, i32, vp, i64, vp]
     lib.sstep_kernel_update.restype = i32
+    lib.sstep_batch_workspace_bytes.argtypes = [i32, sp, i32, i32, op_]
+    lib.sstep_batch_workspace_bytes.restype = C.c_size_t
+    lib.sstep_batch_plan_create.argtypes = [C.POINTER(C.c_void_p), i32, sp, C.POINTER(vp),
+                                            C.POINTER(vp), i32, i32, dp, op_]
+    lib.sstep_batch_plan_create.restype = i32
+    lib.sstep_batch_plan_execute.argtypes = [vp, ip]
+    lib.sstep_batch_plan_execute.restype = i32
+    lib.sstep_batch_plan_destroy.argtypes = [vp]
+    lib.sstep_batch_plan_destroy.restype = None
+    lib.sstep_gmres_solve_batched.argtypes = [i32, sp, C.POINTER(vp), C.POINTER(vp), i32, i32,
+                                              dp, op_, ip]
+    lib.sstep_gmres_solve_batched.restype = i32
     _lib = lib
     return lib
 
@@ -181,7 +197,8 @@ def _stream(stream=None) -> int:
 
 
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
-            workspace=None, stream=None) -> OptionsC:
+            workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
+            batch_graph=False) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -194,6 +211,9 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
         o.workspace = _ptr(workspace)
         o.workspace_bytes = workspace.numel() * workspace.element_size()
     o.stream = _stream(stream)
+    o.batch_threads = int(batch_threads)
+    o.batch_wgs_per_cu = int(batch_wgs_per_cu)
+    o.batch_graph = 1 if batch_graph else 0
     return o
 
 
@@ -269,3 +289,55 @@ def kernel_update(X, Y, M, stream=None) -> None:
     mp = _f64(M, ncx * ncy, "M") if ncx else None
     _check(load().sstep_kernel_update(xp, X.stride(0) if ncx else N, ncx, _f64(Y, ncy * N, "Y"),
                                       Y.stride(0), ncy, mp, N, _stream(stream)), "kernel_update")
+
+
+class BatchPlan:
+    """Batched s-step GMRES(m) over many independent systems in one persistent
+    launch (captured in a hipGraph when graph=True).  stencils: list of
+    Stencil; fs, xs: lists of CUDA float64 tensors (x is overwritten with the
+    solution at every execute(); reset it to the initial guess first)."""
+
+    def __init__(self, stencils, fs, xs, s, m, tol, threads=0, wgs_per_cu=0, graph=True,
+                 max_iters=0, workspace=None):
+        n = len(stencils)
+        if not (len(fs) == len(xs) == n):
+            raise ValueError("stencils, fs and xs must have equal lengths")
+        self.n = n
+        self._A = (StencilC * n)(*[a.c_struct() for a in stencils])
+        self._f = (C.c_void_p * n)(*[_f64(f, a.N, "f") for f, a in zip(fs, stencils)])
+        self._x = (C.c_void_p * n)(*[_f64(x, a.N, "x") for x, a in zip(xs, stencils)])
+        self._keep = (list(fs), list(xs), workspace)
+        o = options(max_iters=max_iters, workspace=workspace, batch_threads=threads,
+                    batch_wgs_per_cu=wgs_per_cu, batch_graph=graph)
+        self._plan = C.c_void_p()
+        _check(load().sstep_batch_plan_create(C.byref(self._plan), n, self._A, self._f, self._x,
+                                              s, m, tol, C.byref(o)), "batch_plan_create")
+
+    def execute(self):
+        infos = (InfoC * self.n)()
+        st = load().sstep_batch_plan_execute(self._plan, infos)
+        if st in (ERR_ARG, ERR_HIP, ERR_NOMEM):   # whole-batch failures
+            _check(st, "batch_plan_execute")
+        # per-system outcomes (including per-system errors) are in the infos
+        return st, [Info.from_c(infos[i]) for i in range(self.n)]
+
+    def close(self):
+        if self._plan:
+            load().sstep_batch_plan_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_workspace_bytes(stencils, s, m, wgs_per_cu=0) -> int:
+    n = len(stencils)
+    arr = (StencilC * n)(*[a.c_struct() for a in stencils])
+    o = StencilC  # noqa: F841
+    opt = OptionsC()
+    load().sstep_default_options(C.byref(opt))
+    opt.batch_wgs_per_cu = int(wgs_per_cu)
+    return int(load().sstep_batch_workspace_bytes(n, arr, s, m, C.byref(opt)))

@@ -1,0 +1,80 @@
+"""Autotuner for the batched persistent solver's launch shape.
+
+Candidate shapes (threads per workgroup x resident workgroups per compute
+unit) are timed on the actual batch -- one warm-up and one timed execution of
+the captured graph each -- and the fastest is cached in a JSON table keyed by
+GPU architecture, batch signature (count, total unknowns, largest system), s
+and m.  The table lives next to this module (``tuned/batched.json``) unless a
+path is given.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import sstep as S
+
+CANDIDATES = ((256, 1), (256, 2), (512, 1), (512, 2), (1024, 1))
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "batched.json")
+
+
+def _arch():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def batch_key(stencils, s, m):
+    sizes = [a.N for a in stencils]
+    return f"{_arch()}|n{len(sizes)}|N{sum(sizes)}|max{max(sizes)}|s{s}|m{m}"
+
+
+def load_cache(path=DEFAULT_CACHE):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(stencils, s, m, path=DEFAULT_CACHE):
+    rec = load_cache(path).get(batch_key(stencils, s, m))
+    return (rec["threads"], rec["wgs_per_cu"]) if rec else None
+
+
+def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAULT_CACHE,
+                 max_iters=0, log=None):
+    """Time every candidate shape on this batch; returns (threads, wgs_per_cu)
+    of the fastest and records all timings in the cache."""
+    import torch
+    wpc_max = max(w for _, w in candidates)
+    nb = S.batch_workspace_bytes(stencils, s, m, wpc_max)
+    ws = torch.empty(nb, dtype=torch.uint8, device=xs[0].device)
+    times = {}
+    for threads, wpc in candidates:
+        plan = S.BatchPlan(stencils, fs, xs, s, m, tol, threads=threads, wgs_per_cu=wpc,
+                           graph=True, max_iters=max_iters, workspace=ws)
+        best = None
+        for _ in range(2):
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.execute()
+            t = time.perf_counter() - t0
+            best = t if best is None else min(best, t)
+        plan.close()
+        times[f"{threads}x{wpc}"] = best
+        if log:
+            log(f"# tune batched: threads={threads} wgs/CU={wpc}: {best * 1e3:.1f} ms")
+    key = min(times, key=times.get)
+    threads, wpc = (int(v) for v in key.split("x"))
+    cache = load_cache(path)
+    cache[batch_key(stencils, s, m)] = {"threads": threads, "wgs_per_cu": wpc,
+                                        "ms": {k: v * 1e3 for k, v in times.items()}}
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
+        json.dump(cache, fh, indent=1, sort_keys=True)
+    del ws
+    return threads, wpc

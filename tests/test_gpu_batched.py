@@ -1,0 +1,138 @@
+"""Batched s-step GMRES (one persistent launch, hipGraph replay) against the
+single-system GPU solver and the FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2001_04886_amd import problems as PB
+from paper_2001_04886_amd import sstep as S
+from helpers import operator
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_batch(n_list, gammas, seed0=100, ndim=2):
+    probs, fs = [], []
+    for i, (n, g) in enumerate(zip(n_list, gammas)):
+        p = PB.convdiff(ndim, n, g, seed=seed0 + i)
+        probs.append(p)
+        fs.append(O.apply(operator(p), p.x_true()))
+    return probs, fs
+
+
+def run_batch(probs, fs, s, m, tol, **kw):
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fd = [torch.from_numpy(f).to(DEV) for f in fs]
+    xd = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
+    plan = S.BatchPlan(st, fd, xd, s, m, tol, **kw)
+    status, infos = plan.execute()
+    torch.cuda.synchronize()
+    xs = [x.cpu().numpy() for x in xd]
+    plan.close()
+    return status, infos, xs
+
+
+SIZES = [33, 8, 64, 17, 40, 5, 50, 24, 12, 3, 45, 29]
+GAMMAS = [10.0, 0.0, 50.0, 80.0, 5.0, 30.0, 99.0, 20.0, 60.0, 1.0, 40.0, 70.0]
+
+
+def test_batched_matches_single_solver_and_oracle():
+    probs, fs = make_batch(SIZES, GAMMAS)
+    status, infos, xs = run_batch(probs, fs, 4, 10, 1e-12, threads=256, graph=True)
+    assert status == S.OK
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        A = operator(p)
+        assert info.status == S.OK and info.rel_resid <= 1e-12
+        r = f - O.apply(A, x)
+        assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-12
+        xo, res = O.sgmres(A, f, np.zeros(p.N), 4, 10, 1e-12)
+        assert rel(x, xo) <= 1e-8, (p.nx, rel(x, xo))
+        assert abs(info.iters - res.iters) <= 1
+        # the single-system GPU solver (same algorithm)
+        xd = torch.zeros(p.N, dtype=torch.float64, device=DEV)
+        si = S.gmres_solve(S.Stencil.from_problem(p), torch.from_numpy(f).to(DEV), xd, 4, 10, 1e-12)
+        assert rel(x, xd.cpu().numpy()) <= 1e-8
+        assert abs(si.iters - info.iters) <= 1
+
+
+def test_batched_fixed_block_count_parity():
+    # run every system for exactly 14 blocks (tol = 0) and compare iterates
+    probs, fs = make_batch(SIZES[:6], GAMMAS[:6], seed0=300)
+    status, infos, xs = run_batch(probs, fs, 4, 6, 0.0, max_iters=14, threads=512)
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        xo, res = O.sgmres(operator(p), f, np.zeros(p.N), 4, 6, 0.0, max_blocks=14)
+        if res.status == O.OK:   # tiny systems may be solved exactly before 14 blocks
+            assert info.status == S.OK
+            continue
+        assert info.iters == res.iters == 14 and info.cycles == res.cycles
+        assert rel(x, xo) <= 1e-8
+
+
+@pytest.mark.parametrize("threads,wpc", [(256, 1), (512, 2), (1024, 1)])
+def test_batched_launch_shapes_agree(threads, wpc):
+    probs, fs = make_batch(SIZES, GAMMAS, seed0=500)
+    status, infos, xs = run_batch(probs, fs, 4, 8, 1e-10, threads=threads, wgs_per_cu=wpc)
+    assert status == S.OK
+    for p, f, x in zip(probs, fs, xs):
+        xo, _ = O.sgmres(operator(p), f, np.zeros(p.N), 4, 8, 1e-12)
+        assert rel(x, xo) <= 1e-7
+
+
+def test_batched_graph_replays_are_identical():
+    probs, fs = make_batch(SIZES, GAMMAS, seed0=700)
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fd = [torch.from_numpy(f).to(DEV) for f in fs]
+    xd = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
+    plan = S.BatchPlan(st, fd, xd, 4, 8, 1e-10, graph=True)
+    ref = None
+    for rep in range(3):
+        for x in xd:
+            x.zero_()
+        # unrelated eager work between replays
+        junk = torch.randn(1 << 20, device=DEV, dtype=torch.float64)
+        (junk * 2).sum().item()
+        status, infos = plan.execute()
+        assert status == S.OK
+        got = [x.cpu().numpy().copy() for x in xd]
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b)
+    plan.close()
+
+
+def test_batched_mixed_dimensions_and_isolation_of_failures():
+    p3 = [PB.convdiff(3, 9, 50.0, seed=1), PB.convdiff(3, 6, 10.0, seed=2)]
+    p2, f2 = make_batch([20, 30], [10.0, 40.0], seed0=900)
+    probs = p3 + p2
+    fs = [O.apply(operator(p), p.x_true()) for p in p3] + f2
+    fs[2] = fs[2].copy()
+    fs[2][5] = np.nan                       # one bad system
+    status, infos, xs = run_batch(probs, fs, 4, 8, 1e-10)
+    assert status == S.ERR_NONFINITE
+    for i, (p, f, x, info) in enumerate(zip(probs, fs, xs, infos)):
+        if i == 2:
+            assert info.status == S.ERR_NONFINITE
+        else:
+            assert info.status == S.OK and info.rel_resid <= 1e-10
+
+
+def test_batched_argument_checks():
+    probs, fs = make_batch([10, 12], [1.0, 2.0])
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fd = [torch.from_numpy(f).to(DEV) for f in fs]
+    xd = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
+    with pytest.raises(S.SstepError):
+        S.BatchPlan(st, fd, xd, 9, 4, 1e-8)          # s > 8
+    with pytest.raises(S.SstepError):
+        S.BatchPlan(st, fd, xd, 8, 65, 1e-8)         # m*s > 512
+    with pytest.raises(S.SstepError):
+        S.BatchPlan(st, fd, xd, 4, 4, 1e-8, threads=300)
