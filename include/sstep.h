@@ -234,6 +234,65 @@ int sstep_kernel_gram(const double *X, int64_t ldx, int ncx, const double *Z, in
 int sstep_kernel_update(const double *X, int64_t ldx, int ncx, double *Y, int64_t ldy,
                         int ncy, const double *M, int64_t N, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned initial guess.  Alg 4.2 restarts from whatever x0 it is given; the
+ * network below proposes one from the problem data of the variable-
+ * coefficient diffusion family  -div(k grad u) = f  on an nx x ny grid
+ * (extension beyond the paper, which always starts from a fixed x0).
+ *
+ * Network: input channels (log k, f / rms(f)) per grid point, rms over the
+ * grid of one sample; four dilated 3x3 convolutions with channels
+ * 2 -> 32 -> 32 -> 32 -> 1, dilations 1, 2, 4, 8, zero padding equal to the
+ * dilation, ReLU after the first three; x0 = out * rms(f) * out_scale.
+ * Training loss: mean over all points of the batch of
+ * (out - x / (rms(f) * out_scale))^2; optimiser Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected).
+ *
+ * params: DEVICE float[sstep_cnn_param_count()] = 19393, layer by layer
+ * W_l[Cout][Cin][3][3] then b_l[Cout].  Activations are stored in bf16 with
+ * FP32 accumulation; the two 32 -> 32 layers run on bf16 matrix cores.
+ *
+ * Batched arrays are DEVICE [batch][ny][nx] (x fastest), 16-byte aligned:
+ * logk float, f and x double.  Every call enqueues on opt->stream and returns
+ * after completion.  Workspace: opt->workspace of at least
+ * sstep_cnn_workspace_bytes(batch, nx, ny, training) bytes (16-byte aligned),
+ * or NULL for a temporary allocation.  Errors: SSTEP_ERR_ARG for bad sizes,
+ * pointers, alignment or a non-positive out_scale / lr; SSTEP_ERR_NOMEM,
+ * SSTEP_ERR_HIP.  The caller owns every pointer.
+ * ---------------------------------------------------------------------- */
+size_t sstep_cnn_param_count(void);
+size_t sstep_cnn_workspace_bytes(int batch, int nx, int ny, int training);
+
+/* Forward pass: out (float [batch][ny][nx], raw network output, may be NULL)
+ * and/or x0 (double, the scaled guess, may be NULL; not both NULL). */
+int sstep_cnn_forward(const float *params, double out_scale, int batch, int nx, int ny,
+                      const float *logk, const double *f, float *out, double *x0,
+                      const sstep_options *opt);
+
+/* Loss (HOST double, may be NULL) and its gradient grad (DEVICE float
+ * [param_count]) for targets x (the solutions of the batch). */
+int sstep_cnn_gradient(const float *params, double out_scale, int batch, int nx, int ny,
+                       const float *logk, const double *f, const double *x, float *grad,
+                       double *loss, const sstep_options *opt);
+
+/* One Adam step (step >= 1 counts updates, for the bias correction) on
+ * params with moments m, v (DEVICE float[param_count], zero before step 1). */
+int sstep_cnn_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                   const sstep_options *opt);
+
+/* sstep_cnn_gradient followed by sstep_cnn_adam, sharing the workspace. */
+int sstep_cnn_train_step(float *params, float *m, float *v, int step, float lr,
+                         double out_scale, int batch, int nx, int ny, const float *logk,
+                         const double *f, const double *x, double *loss,
+                         const sstep_options *opt);
+
+/* Initial guess for one 2-D system A x = f (A: ndim 2, stencil of the same
+ * grid; logk and f DEVICE [ny][nx]).  With use_fallback != 0, x0 is reset to
+ * 0 when ||f - A x0|| >= ||f|| and *used_fallback (HOST, may be NULL) says so. */
+int sstep_x0_predict(const float *params, double out_scale, const sstep_stencil *A,
+                     const float *logk, const double *f, double *x0, int use_fallback,
+                     int *used_fallback, const sstep_options *opt);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,8 @@ EXPORTS = (
     "sstep_kernel_mpk", "sstep_kernel_gram", "sstep_kernel_update",
     "sstep_batch_workspace_bytes", "sstep_batch_plan_create", "sstep_batch_plan_execute",
     "sstep_batch_plan_destroy", "sstep_gmres_solve_batched",
+    "sstep_cnn_param_count", "sstep_cnn_workspace_bytes", "sstep_cnn_forward",
+    "sstep_cnn_gradient", "sstep_cnn_adam", "sstep_cnn_train_step", "sstep_x0_predict",
 )
 
 
@@ -100,6 +102,22 @@ def load(path: str | None = None):
     lib.sstep_gmres_solve_batched.argtypes = [i32, sp, C.POINTER(vp), C.POINTER(vp), i32, i32,
                                               dp, op_, ip]
     lib.sstep_gmres_solve_batched.restype = i32
+    lib.sstep_cnn_param_count.argtypes = []
+    lib.sstep_cnn_param_count.restype = C.c_size_t
+    lib.sstep_cnn_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.sstep_cnn_workspace_bytes.restype = C.c_size_t
+    lib.sstep_cnn_forward.argtypes = [vp, dp, i32, i32, i32, vp, vp, vp, vp, op_]
+    lib.sstep_cnn_forward.restype = i32
+    lib.sstep_cnn_gradient.argtypes = [vp, dp, i32, i32, i32, vp, vp, vp, vp,
+                                       C.POINTER(C.c_double), op_]
+    lib.sstep_cnn_gradient.restype = i32
+    lib.sstep_cnn_adam.argtypes = [vp, vp, vp, vp, i32, C.c_float, op_]
+    lib.sstep_cnn_adam.restype = i32
+    lib.sstep_cnn_train_step.argtypes = [vp, vp, vp, i32, C.c_float, dp, i32, i32, i32, vp, vp,
+                                         vp, C.POINTER(C.c_double), op_]
+    lib.sstep_cnn_train_step.restype = i32
+    lib.sstep_x0_predict.argtypes = [vp, dp, sp, vp, vp, vp, i32, C.POINTER(C.c_int), op_]
+    lib.sstep_x0_predict.restype = i32
     _lib = lib
     return lib
 
@@ -341,3 +359,92 @@ def batch_workspace_bytes(stencils, s, m, wgs_per_cu=0) -> int:
     load().sstep_default_options(C.byref(opt))
     opt.batch_wgs_per_cu = int(wgs_per_cu)
     return int(load().sstep_batch_workspace_bytes(n, arr, s, m, C.byref(opt)))
+
+
+# ---------------------------------------------------------------------------
+# learned initial guess (include/sstep.h, sstep_cnn_* and sstep_x0_predict)
+# ---------------------------------------------------------------------------
+
+def _f32(t, n, name):
+    import torch
+    if t.dtype != torch.float32 or t.numel() < n:
+        raise ValueError(f"{name} must be a float32 tensor with >= {n} elements")
+    return _ptr(t)
+
+
+def _bhw(t):
+    """(batch, ny, nx) of a [B][ny][nx] or [ny][nx] tensor."""
+    if t.dim() == 2:
+        return 1, t.shape[0], t.shape[1]
+    if t.dim() == 3:
+        return t.shape[0], t.shape[1], t.shape[2]
+    raise ValueError("expected a [B][ny][nx] or [ny][nx] tensor")
+
+
+def cnn_param_count() -> int:
+    return int(load().sstep_cnn_param_count())
+
+
+def cnn_workspace_bytes(batch: int, nx: int, ny: int, training: bool) -> int:
+    return int(load().sstep_cnn_workspace_bytes(batch, nx, ny, 1 if training else 0))
+
+
+def cnn_forward(params, out_scale, logk, f, out=None, x0=None, workspace=None, stream=None):
+    """Network output (float32, optional) and scaled guess x0 (float64, optional)."""
+    B, ny, nx = _bhw(logk)
+    n = B * ny * nx
+    o = options(workspace=workspace, stream=stream)
+    _check(load().sstep_cnn_forward(
+        _f32(params, cnn_param_count(), "params"), float(out_scale), B, nx, ny,
+        _f32(logk, n, "logk"), _f64(f, n, "f"), _f32(out, n, "out") if out is not None else None,
+        _f64(x0, n, "x0") if x0 is not None else None, C.byref(o)), "cnn_forward")
+
+
+def cnn_gradient(params, out_scale, logk, f, x, grad, workspace=None, stream=None) -> float:
+    """Loss and its parameter gradient (into grad, float32) for targets x."""
+    B, ny, nx = _bhw(logk)
+    n = B * ny * nx
+    loss = C.c_double(0.0)
+    o = options(workspace=workspace, stream=stream)
+    _check(load().sstep_cnn_gradient(
+        _f32(params, cnn_param_count(), "params"), float(out_scale), B, nx, ny,
+        _f32(logk, n, "logk"), _f64(f, n, "f"), _f64(x, n, "x"),
+        _f32(grad, cnn_param_count(), "grad"), C.byref(loss), C.byref(o)), "cnn_gradient")
+    return loss.value
+
+
+def cnn_adam(params, m, v, grad, step: int, lr: float, stream=None) -> None:
+    P = cnn_param_count()
+    o = options(stream=stream)
+    _check(load().sstep_cnn_adam(_f32(params, P, "params"), _f32(m, P, "m"), _f32(v, P, "v"),
+                                 _f32(grad, P, "grad"), int(step), float(lr), C.byref(o)),
+           "cnn_adam")
+
+
+def cnn_train_step(params, m, v, step: int, lr: float, out_scale, logk, f, x, workspace=None,
+                   stream=None) -> float:
+    """One Adam step on a batch; returns the batch loss before the step."""
+    B, ny, nx = _bhw(logk)
+    n = B * ny * nx
+    P = cnn_param_count()
+    loss = C.c_double(0.0)
+    o = options(workspace=workspace, stream=stream)
+    _check(load().sstep_cnn_train_step(
+        _f32(params, P, "params"), _f32(m, P, "m"), _f32(v, P, "v"), int(step), float(lr),
+        float(out_scale), B, nx, ny, _f32(logk, n, "logk"), _f64(f, n, "f"), _f64(x, n, "x"),
+        C.byref(loss), C.byref(o)), "cnn_train_step")
+    return loss.value
+
+
+def x0_predict(params, out_scale, A: Stencil, logk, f, x0, use_fallback=True, workspace=None,
+               stream=None) -> bool:
+    """Fill x0 with the network's guess for A x = f; returns True when the
+    fallback rule replaced it by zero."""
+    sc = A.c_struct()
+    used = C.c_int(0)
+    o = options(workspace=workspace, stream=stream)
+    _check(load().sstep_x0_predict(
+        _f32(params, cnn_param_count(), "params"), float(out_scale), C.byref(sc),
+        _f32(logk, A.N, "logk"), _f64(f, A.N, "f"), _f64(x0, A.N, "x0"),
+        1 if use_fallback else 0, C.byref(used), C.byref(o)), "x0_predict")
+    return bool(used.value)
