@@ -82,11 +82,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the GMRES(ms) comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-blocks", type=int, default=2)
-    ap.add_argument("--workload", choices=["gmres3d", "mixed3d", "omin2d", "small2d", "batched"],
+    ap.add_argument("--workload", choices=["gmres3d", "mixed3d", "omin2d", "small2d", "batched",
+                                           "learned"],
                     default="gmres3d")
     ap.add_argument("--nsys", type=int, default=512)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--omin-iters", type=int, default=200)
+    ap.add_argument("--eval-samples", type=int, default=16)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -444,8 +446,90 @@ def bench_batched(args):
                         "traffic": None}})
 
 
+def bench_learned(args):
+    """Learned initial guess on 256^2 variable-coefficient diffusion: s-step
+    GMRES(m=30, s=8) to 1e-8 from x0 = 0, from the trained network's guess
+    with the fallback rule, and from the raw guess, on held-out seeded fields
+    (the trained model is the committed one)."""
+    import numpy as np
+    import torch
+    from paper_2001_04886_amd import learn as LN
+    from paper_2001_04886_amd import sstep as S
+    dev = torch.device("cuda:0")
+    params, out_scale, meta = LN.load_model()
+    log = lambda *a: print("#", *a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.warmup:
+        wds = LN.generate(1, 9000, nstreams=1, log=log)
+        LN.evaluate(params, out_scale, wds, log=log)
+    ds = LN.generate(args.eval_samples, 5000, nstreams=1, log=log)
+    res = LN.evaluate(params, out_scale, ds, log=log)
+    summ = {}
+    for mode in ("zero", "cnn", "cnn_nofallback"):
+        r = res[mode]
+        summ[mode] = {"mean_s": float(r["seconds"].mean()), "mean_blocks": float(r["blocks"].mean()),
+                      "converged_all": bool(np.all(r["status"] == S.OK))}
+    fb = float(res["fallback"].mean())
+    # the network's own speed: forward (inference) at batch 32 and one
+    # training step, timed with events on the stream the kernels run on
+    B, n = 32, LN.GRID
+    pdev = torch.as_tensor(params, device=dev)
+    lk = ds.logk[:1].expand(B, n, n).contiguous()
+    f = ds.f[:1].expand(B, n, n).contiguous()
+    x = ds.x[:1].expand(B, n, n).contiguous()
+    x0 = torch.empty_like(f)
+    wsf = torch.empty(S.cnn_workspace_bytes(B, n, n, False), dtype=torch.uint8, device=dev)
+    wst = torch.empty(S.cnn_workspace_bytes(B, n, n, True), dtype=torch.uint8, device=dev)
+    g = torch.zeros_like(pdev)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    for _ in range(3):
+        S.cnn_forward(pdev, out_scale, lk, f, x0=x0, workspace=wsf)
+    e0.record(st)
+    for _ in range(reps):
+        S.cnn_forward(pdev, out_scale, lk, f, x0=x0, workspace=wsf)
+    e1.record(st)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    e0.record(st)
+    for _ in range(reps):
+        S.cnn_gradient(pdev, out_scale, lk, f, x, g, workspace=wst)
+    e1.record(st)
+    e1.synchronize()
+    grad_ms = e0.elapsed_time(e1) / reps
+    fwd_flop = 2.0 * n * n * 9 * (2 * 32 + 32 * 32 * 2 + 32)  # per sample, all four layers
+    tf_fwd = fwd_flop * B / (fwd_ms * 1e-3) / 1e12
+    tf_grad = 3.0 * fwd_flop * B / (grad_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        import oracle.cnn as OC
+        t0 = time.perf_counter()
+        OC.forward(params.astype(np.float64), ds.logk[:1].cpu().numpy(), ds.f[:1].cpu().numpy())
+        tcf = time.perf_counter() - t0
+        cpu = {"value": tcf, "unit": "s per 256^2 forward", "cores": 1, "kind": "oracle",
+               "sample": "FP64 oracle network forward on one held-out 256^2 sample, 1 thread "
+                         f"(GPU batch-32 forward: {fwd_ms / B:.4f} ms per sample)"}
+    v = summ["cnn"]["mean_s"]
+    _line("s-step GMRES(30,8) time to 1e-8 from the learned x0 (with fallback), 256^2 diffusion",
+          v, "s", False, v * 1e3, args, "f64+bf16",
+          f"2-D 5-pt -div(k grad u)=f, 256^2, log k and f squared-exponential GRFs (length 0.1), "
+          f"{args.eval_samples} held-out seeds; s-GMRES(m=30, s=8) FP64 tol 1e-8; network 2-32-32-32-1 "
+          f"dilated 3x3, bf16 storage / FP32 accumulation, trained on {meta.get('samples')} solved "
+          f"systems x 8 grid symmetries",
+          {"results": summ, "fallback_rate": fb,
+           "blocks_ratio_nofallback": summ["cnn_nofallback"]["mean_blocks"] / summ["zero"]["mean_blocks"],
+           "time_ratio_vs_zero": v / summ["zero"]["mean_s"],
+           "model": {k: meta.get(k) for k in ("samples", "epochs", "batch", "lr", "steps")},
+           "cnn": {"forward_ms_batch32": fwd_ms, "gradient_ms_batch32": grad_ms,
+                   "forward_TFLOPs": tf_fwd, "gradient_TFLOPs": tf_grad},
+           "roofline": {"bound": "mfma", "kernel": "network forward, batch 32 (all layers)",
+                        "achieved": tf_fwd, "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": tf_fwd / 2500.0, "traffic": None},
+           "cpu_baseline": cpu})
+
+
 OTHER = {"mixed3d": bench_mixed3d, "omin2d": bench_omin2d, "small2d": bench_small2d,
-         "batched": bench_batched}
+         "batched": bench_batched, "learned": bench_learned}
 
 
 if __name__ == "__main__":

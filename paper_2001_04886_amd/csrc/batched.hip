@@ -37,6 +37,7 @@ struct BatchSys {
     double sigma;
     int status, blocks, cycles, pad;
     double rel_resid;
+    long long ticks[SSTEP_K_NCLASS];  // wall-clock ticks of the owning workgroup per class
 };
 
 // per-workgroup scratch for the small dense state (sized for m*s <= 512)
@@ -76,6 +77,24 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     for (int w = 0; w < NT / 64; ++w) t += red[w];
     return t;
 }
+
+// Phase timer of the owning workgroup: thread 0 reads the constant-rate wall
+// clock after the barrier that closes a phase and charges the interval to one
+// kernel class (matrix powers, Gram, update, residual, scalar work, vector).
+struct PhaseClock {
+    long long t0 = 0;
+    long long acc[SSTEP_K_NCLASS] = {0, 0, 0, 0, 0, 0};
+    __device__ void start() {
+        if (threadIdx.x == 0) t0 = wall_clock64();
+    }
+    __device__ void lap(int cls) {
+        if (threadIdx.x == 0) {
+            const long long t = wall_clock64();
+            acc[cls] += t - t0;
+            t0 = t;
+        }
+    }
+};
 
 // one stencil level over all points of a system: out = a*(A y) with y = in*sc
 __device__ __forceinline__ double stencil_at(const StencilView& A, const double* in, long long p,
@@ -149,10 +168,13 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
     // Basis change B (monomial): A Y[:,0:s] = Y B with B[j+1][j] = sigma
     const double sigma = S.sigma;
 
+    PhaseClock pc;
+    pc.start();
     // ||f||
     double acc = 0.0;
     for (long long p = tid; p < N; p += NT) acc += S.f[p] * S.f[p];
     const double fnorm = sqrt(wg_sum<NT>(acc, red));
+    pc.lap(SSTEP_K_VEC);
     const double tol_abs = args.tol * fnorm;
     int blocks = 0, cycles = 0, status = SSTEP_NOT_CONVERGED;
     double beta = 0.0;
@@ -166,6 +188,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
             acc += r * r;
         }
         beta = sqrt(wg_sum<NT>(acc, red));
+        pc.lap(SSTEP_K_RESID);
         if (!isfinite(beta)) { status = SSTEP_ERR_NONFINITE; break; }
         if (beta <= tol_abs) { status = SSTEP_OK; break; }
         if (blocks >= args.max_blocks) { status = SSTEP_NOT_CONVERGED; break; }
@@ -192,9 +215,11 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 }
                 __syncthreads();
             }
+            pc.lap(SSTEP_K_MPK);
             if (kb > 0) {
                 // C = V_prev^T [y_1..y_s]
                 wg_gram<NT, CA, KZ>(V, ld, c0, Yk + ld, ld, s, N, W.C, red);
+                pc.lap(SSTEP_K_GRAM);
                 // T_i = W_i^{-1} C_i, update coefficients
                 for (int idx = tid; idx < kb * s; idx += NT) {
                     const int i = idx / s, l = idx % s + 1;
@@ -209,6 +234,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                     }
                 }
                 __syncthreads();
+                pc.lap(SSTEP_K_SCALAR);
                 // y_j -= sum_c V_c coefM[c][j]
                 for (long long p = tid; p < N; p += NT) {
                     double a[KZ];
@@ -225,9 +251,11 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                         if (l < s) Yk[(long long)(l + 1) * ld + p] = a[l];
                 }
                 __syncthreads();
+                pc.lap(SSTEP_K_UPDATE);
             }
             // block Gram of [w_k, y_1..y_s]
             wg_gram<NT, CA, KZ + 1>(Yk, ld, s1, Yk, ld, s1, N, W.C, red);
+            pc.lap(SSTEP_K_GRAM);
             // Scalar1: factor W_k in LDS (one thread), copy the factor out
             if (tid == 0) {
                 const double d0 = W.inv_nu[kb];
@@ -257,6 +285,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 for (int i = tid; i < (int)(sizeof(GramFactor) / sizeof(double)); i += NT) dst[i] = src[i];
             }
             __syncthreads();
+            pc.lap(SSTEP_K_SCALAR);
             const int q = W.Wf[kb].rank;
             if (q == 0) { err = true; break; }
             double nu = 0.0;
@@ -274,6 +303,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 }
                 nu = sqrt(wg_sum<NT>(acc, red));
             }
+            pc.lap(SSTEP_K_VEC);
             const bool lucky = (q == s) && !(nu > args.lucky_tol * sqrt(sh[2 * kMaxS]));
             // Hessenberg block column, rows 0..c0+q
             for (int idx = tid; idx < q * (c0 + q + 1); idx += NT) {
@@ -350,6 +380,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 sh[2 * kMaxS + 1] = fabs(W.rhs[c0 + q]);
             }
             __syncthreads();
+            pc.lap(SSTEP_K_SCALAR);
             ncols = c0 + q;
             ++blocks;
             const double est = sh[2 * kMaxS + 1];
@@ -373,12 +404,14 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
             S.x[p] = v;
         }
         __syncthreads();
+        pc.lap(SSTEP_K_UPDATE);
     }
     if (tid == 0) {
         S.status = status;
         S.blocks = blocks;
         S.cycles = cycles;
         S.rel_resid = fnorm > 0.0 ? beta / fnorm : beta;
+        for (int c = 0; c < SSTEP_K_NCLASS; ++c) S.ticks[c] = pc.acc[c];
     }
     __syncthreads();
 }
@@ -410,6 +443,7 @@ static __global__ void k_batch_reset(int* queue) { *queue = 0; }
 // ---------------------------------------------------------------------------
 struct BatchPlan {
     int nsys = 0, s = 0, m = 0, threads = 512, wgs_per_cu = 1, nslots = 0;
+    double tick_khz = 1e5;  // wall-clock rate of the device (kHz)
     hipStream_t st = nullptr;
     void* ws = nullptr;
     bool owned = false;
@@ -463,6 +497,14 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
     P->wgs_per_cu = opt.batch_wgs_per_cu > 0 ? opt.batch_wgs_per_cu : 1;
     P->nslots = batched_slots(nsys, P->wgs_per_cu);
     P->st = (hipStream_t)opt.stream;
+    {
+        int dev = 0, khz = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            P->tick_khz = khz;
+        else
+            (void)hipGetLastError();
+    }
     const size_t need = batched_workspace_bytes(nsys, A, s, m, P->nslots);
     if (opt.workspace) {
         if (opt.workspace_bytes < need || ((uintptr_t)opt.workspace & 255u)) {
@@ -571,6 +613,7 @@ int batched_plan_execute(void* plan, sstep_info* info, double* ms_out) {
             info[i].rel_resid = b.rel_resid;
             info[i].sigma = b.sigma;
             info[i].ms_total = ms;
+            for (int c = 0; c < SSTEP_K_NCLASS; ++c) info[i].ms[c] = (double)b.ticks[c] / P->tick_khz;
         }
         if (b.status < 0 && status >= 0) status = b.status;
         else if (b.status == SSTEP_NOT_CONVERGED && status == SSTEP_OK) status = SSTEP_NOT_CONVERGED;

@@ -1,0 +1,298 @@
+"""Learned initial guess: training-data generation, training and evaluation.
+
+Alg 4.2 (restarted s-step GMRES) starts from an arbitrary x0.  This module
+trains the network of ``sstep_cnn_*`` (include/sstep.h) to propose x0 for the
+variable-coefficient diffusion family -div(k grad u) = f on a 256 x 256 grid,
+with log k and f squared-exponential Gaussian random fields (correlation
+length 0.1, unit variance), and measures what the guess buys the solver.
+
+Everything numeric runs in the HIP library: the solves that produce the
+training targets (sstep_gmres_solve), the network's forward/backward/Adam
+(sstep_cnn_train_step) and the guess with its fallback test
+(sstep_x0_predict).  This module only generates seeded inputs (through
+problems.py), moves batches, and keeps the books.
+
+Command line (on a GPU):
+    python -m paper_2001_04886_amd.learn --samples 2048 --epochs 40 --out model.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import threading
+import time
+
+import numpy as np
+
+from . import problems as P
+from . import sstep as S
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_MODEL = os.path.join(_HERE, "tuned", "x0_cnn.npz")
+GRID = 256
+CORR_LENGTH = 0.1
+SOLVE_S, SOLVE_M, SOLVE_TOL = 8, 30, 1e-8
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+class Dataset:
+    """Samples on the device: logk float32 [S][n][n], f and x float64."""
+
+    def __init__(self, logk, f, x, blocks, seconds, seed):
+        self.logk, self.f, self.x = logk, f, x
+        self.blocks, self.seconds, self.seed = blocks, seconds, seed
+
+    def __len__(self):
+        return self.logk.shape[0]
+
+
+def sample_inputs(count, seed, n=GRID, device="cuda:0"):
+    """log k (float32) and f (float64) fields for ``count`` samples; the two
+    fields of a sample come from independent generator streams."""
+    import torch
+    logk = P.grf_batch_torch(n, CORR_LENGTH, 2 * seed, count, device=device).to(torch.float32)
+    f = P.grf_batch_torch(n, CORR_LENGTH, 2 * seed + 1, count, device=device)
+    return logk.contiguous(), f.contiguous()
+
+
+def stencil_for(logk_sample):
+    """Stencil descriptor + its [7][N] coefficient tensor (kept alive by the
+    caller) for one log k field."""
+    coef = P.diffusion_coef_torch(logk_sample).contiguous()
+    n = logk_sample.shape[0]
+    return S.Stencil(2, n, n, 1, (0.0,) * 7, coef), coef
+
+
+def solve_all(logk, f, x, s=SOLVE_S, m=SOLVE_M, tol=SOLVE_TOL, nstreams=4, x0_fn=None,
+              log=_log):
+    """Solve every sample with s-step GMRES(m) on ``nstreams`` concurrent
+    streams (one host thread each; the library waits on its own stream).
+    x holds the initial guesses on entry (or x0_fn(i, A, stream) fills them)
+    and the solutions on return.  Returns per-sample (blocks, status, seconds)."""
+    import torch
+    count = logk.shape[0]
+    n = logk.shape[1]
+    blocks = np.zeros(count, dtype=np.int64)
+    status = np.zeros(count, dtype=np.int64)
+    secs = np.zeros(count)
+    done = [0]
+    lock = threading.Lock()
+    errors = []
+    A0, _ = stencil_for(logk[0])
+    ws_bytes = S.workspace_bytes(A0, S.METHOD_GMRES, s, m)
+
+    def worker(t):
+        try:
+            st = torch.cuda.Stream(device=logk.device)
+            ws = torch.empty(ws_bytes, dtype=torch.uint8, device=logk.device)
+            with torch.cuda.stream(st):
+                for i in range(t, count, nstreams):
+                    A, coef = stencil_for(logk[i])
+                    t0 = time.perf_counter()
+                    if x0_fn is not None:
+                        x0_fn(i, A, st)
+                    info = S.gmres_solve(A, f[i].reshape(-1), x[i].reshape(-1), s, m, tol,
+                                         workspace=ws, stream=st)
+                    secs[i] = time.perf_counter() - t0
+                    blocks[i], status[i] = info.iters, info.status
+                    del coef
+                    with lock:
+                        done[0] += 1
+                        if done[0] % 64 == 0 or done[0] == count:
+                            log(f"  solved {done[0]}/{count}")
+        except Exception as e:  # surfaced after join
+            errors.append(e)
+
+    torch.cuda.synchronize()
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(nstreams)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    torch.cuda.synchronize()
+    if errors:
+        raise errors[0]
+    return blocks, status, secs
+
+
+def generate(count, seed, n=GRID, nstreams=4, device="cuda:0", log=_log):
+    """Training/evaluation samples: seeded fields and their s-step GMRES
+    solutions to the solver tolerance from x0 = 0."""
+    import torch
+    t0 = time.perf_counter()
+    logk, f = sample_inputs(count, seed, n, device)
+    x = torch.zeros_like(f)
+    log(f"generating {count} samples (seed {seed}) on {nstreams} streams")
+    blocks, status, secs = solve_all(logk, f, x, nstreams=nstreams, log=log)
+    bad = int(np.sum(status != S.OK))
+    log(f"generated {count} samples in {time.perf_counter() - t0:.1f} s; "
+        f"mean blocks {blocks.mean():.0f}; not converged {bad}")
+    return Dataset(logk, f, x, blocks, secs, seed)
+
+
+def out_scale_of(ds, nsamp=64):
+    """rms over samples of x / rms(f): the output scale that makes the
+    regression target O(1) (a model constant)."""
+    k = min(nsamp, len(ds))
+    x = ds.x[:k].double().cpu().numpy().reshape(k, -1)
+    f = ds.f[:k].double().cpu().numpy().reshape(k, -1)
+    fr = np.sqrt(np.mean(f * f, axis=1))
+    return float(np.sqrt(np.mean((x / fr[:, None]) ** 2)))
+
+
+def init_params(seed=0):
+    """He-normal weights, zero biases, in the flat layout of sstep_cnn_*."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for co, ci in ((32, 2), (32, 32), (32, 32), (1, 32)):
+        parts.append(rng.standard_normal(co * ci * 9) * np.sqrt(2.0 / (9 * ci)))
+        parts.append(np.zeros(co))
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == S.cnn_param_count()
+    return p
+
+
+def symmetry(t, g):
+    """Element g (0..7) of the symmetry group of the square grid applied to a
+    batch [B][n][n]: g % 4 quarter turns, then a transpose when g >= 4.  The
+    harmonic-mean diffusion stencil is equivariant under all eight, so a
+    solved (k, f, x) maps to another solved sample; so does (k, -f, -x)."""
+    import torch
+    t = torch.rot90(t, g % 4, dims=(1, 2))
+    if g >= 4:
+        t = t.transpose(1, 2)
+    return t.contiguous()
+
+
+def train(ds, epochs, batch=32, lr=1e-3, seed=0, val=None, augment=True, log=_log):
+    """Adam on the mean-squared error against x / (rms(f) out_scale); each
+    batch is drawn under a random grid symmetry and sign (augment=True)."""
+    import torch
+    dev = ds.logk.device
+    n = ds.logk.shape[1]
+    out_scale = out_scale_of(ds)
+    params = torch.tensor(init_params(seed), device=dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    ws = torch.empty(S.cnn_workspace_bytes(batch, n, n, True), dtype=torch.uint8, device=dev)
+    grad = torch.zeros_like(params)
+    rng = np.random.default_rng(seed + 1)
+    step = 0
+    hist = []
+    t0 = time.perf_counter()
+    nb = len(ds) // batch
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(len(ds))[: nb * batch], device=dev)
+        losses = []
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            step += 1
+            g = int(rng.integers(8)) if augment else 0
+            sign = float(rng.choice((-1.0, 1.0))) if augment else 1.0
+            lk, f, x = (symmetry(t[idx], g) for t in (ds.logk, ds.f, ds.x))
+            losses.append(S.cnn_train_step(params, m, v, step, lr, out_scale, lk, f * sign,
+                                           x * sign, workspace=ws))
+        rec = {"epoch": ep + 1, "train_loss": float(np.mean(losses))}
+        if val is not None:
+            vl = []
+            for b in range(0, len(val) - batch + 1, batch):
+                vl.append(S.cnn_gradient(params, out_scale, val.logk[b:b + batch].contiguous(),
+                                         val.f[b:b + batch].contiguous(),
+                                         val.x[b:b + batch].contiguous(), grad, workspace=ws))
+            rec["val_loss"] = float(np.mean(vl)) if vl else None
+        hist.append(rec)
+        log(f"  epoch {ep + 1}/{epochs}: " + ", ".join(
+            f"{k} {v_:.4e}" for k, v_ in rec.items() if k != "epoch" and v_ is not None)
+            + f"  ({time.perf_counter() - t0:.1f} s)")
+    train_s = time.perf_counter() - t0
+    return params.cpu().numpy(), out_scale, hist, train_s, step
+
+
+def save_model(path, params, out_scale, meta):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, params=np.asarray(params, dtype=np.float32),
+             out_scale=np.float64(out_scale), meta=np.array(json.dumps(meta)))
+
+
+def load_model(path=DEFAULT_MODEL):
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), float(z["out_scale"]), json.loads(str(z["meta"]))
+
+
+def evaluate(params, out_scale, ds, nstreams=1, log=_log):
+    """Solve every sample of ``ds`` from x0 = 0, from the network's guess with
+    the fallback rule, and from the raw guess; returns per-sample blocks and
+    wall seconds (guess included) for each, and the fallback flags."""
+    import torch
+    dev = ds.logk.device
+    n = ds.logk.shape[1]
+    pdev = torch.as_tensor(params, device=dev)
+    count = len(ds)
+    ws = [torch.empty(S.cnn_workspace_bytes(1, n, n, False), dtype=torch.uint8, device=dev)
+          for _ in range(nstreams)]
+    fallback = np.zeros(count, dtype=bool)
+    res = {}
+    for mode in ("zero", "cnn", "cnn_nofallback"):
+        x = torch.zeros_like(ds.f)
+
+        def x0_fn(i, A, st, mode=mode):
+            if mode == "zero":
+                return
+            used = S.x0_predict(pdev, out_scale, A, ds.logk[i].reshape(-1), ds.f[i].reshape(-1),
+                                x[i].reshape(-1), use_fallback=(mode == "cnn"),
+                                workspace=ws[i % nstreams], stream=st)
+            if mode == "cnn":
+                fallback[i] = used
+
+        blocks, status, secs = solve_all(ds.logk, ds.f, x, nstreams=nstreams, x0_fn=x0_fn,
+                                         log=lambda *a: None)
+        res[mode] = {"blocks": blocks, "status": status, "seconds": secs}
+        log(f"  eval {mode}: mean blocks {blocks.mean():.1f}, mean time {secs.mean() * 1e3:.1f} ms, "
+            f"not converged {int(np.sum(status != S.OK))}")
+    res["fallback"] = fallback
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--samples", type=int, default=2048)
+    ap.add_argument("--val", type=int, default=128)
+    ap.add_argument("--eval", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--out", default=DEFAULT_MODEL)
+    args = ap.parse_args(argv)
+    import torch
+    S.load()
+    dev = "cuda:0"
+    torch.cuda.init()
+    train_ds = generate(args.samples, args.seed, nstreams=args.streams, device=dev)
+    val_ds = generate(args.val, args.seed + 1, nstreams=args.streams, device=dev)
+    params, out_scale, hist, train_s, steps = train(train_ds, args.epochs, args.batch, args.lr,
+                                                    val=val_ds)
+    meta = {"grid": GRID, "samples": args.samples, "val": args.val, "epochs": args.epochs,
+            "batch": args.batch, "lr": args.lr, "seed": args.seed, "steps": steps,
+            "train_seconds": train_s, "history": hist,
+            "data_mean_blocks": float(train_ds.blocks.mean()),
+            "data_seconds": float(train_ds.seconds.sum())}
+    save_model(args.out, params, out_scale, meta)
+    _log(f"saved {args.out} (out_scale {out_scale:.4e})")
+    del train_ds
+    ev_ds = generate(args.eval, args.seed + 2, nstreams=args.streams, device=dev)
+    res = evaluate(params, out_scale, ev_ds)
+    summary = {m: {"mean_blocks": float(res[m]["blocks"].mean()),
+                   "mean_ms": float(res[m]["seconds"].mean() * 1e3)}
+               for m in ("zero", "cnn", "cnn_nofallback")}
+    summary["fallback_rate"] = float(res["fallback"].mean())
+    _log("EVAL " + json.dumps(summary))
+
+
+if __name__ == "__main__":
+    main()

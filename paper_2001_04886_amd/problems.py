@@ -164,3 +164,61 @@ def diffusion_coef(logk: np.ndarray) -> np.ndarray:
     coef[3] = (-ks / h2).ravel()
     coef[4] = (-kn / h2).ravel()
     return coef
+
+
+# ---------------------------------------------------------------------------
+# Device-side variants for the learned-initial-guess data (many 256^2 samples):
+# the same field and stencil recipes as grf / diffusion_coef, built with torch
+# on the GPU so that thousands of samples do not wait on host FFTs.  Noise
+# comes from torch's seeded generator, so the fields differ from grf's (numpy
+# PCG64) for the same seed; statistics and coefficients follow the same recipe.
+# ---------------------------------------------------------------------------
+
+def grf_batch_torch(n: int, length: float, seed: int, count: int, device="cuda", pad: int = 2):
+    """count unit-variance squared-exponential Gaussian random fields on an
+    n x n grid (spectral synthesis on a (pad*n)^2 periodic grid, cropped);
+    float64 tensor [count][n][n], each normalised to mean 0, std 1."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    m = pad * n
+    h = 1.0 / (n + 1)
+    k = torch.fft.fftfreq(m, d=h, dtype=torch.float64, device=device) * 2.0 * np.pi
+    ky, kx = torch.meshgrid(k, k, indexing="ij")
+    amp = torch.exp(-0.25 * (kx ** 2 + ky ** 2) * length ** 2)  # sqrt of the spectral density
+    out = torch.empty((count, n, n), dtype=torch.float64, device=device)
+    chunk = 64
+    for c0 in range(0, count, chunk):
+        c1 = min(count, c0 + chunk)
+        re = torch.randn((c1 - c0, m, m), generator=gen, dtype=torch.float64, device=device)
+        im = torch.randn((c1 - c0, m, m), generator=gen, dtype=torch.float64, device=device)
+        field = torch.fft.ifft2(torch.complex(re, im) * amp).real[:, :n, :n]
+        mu = field.mean(dim=(1, 2), keepdim=True)
+        sd = field.std(dim=(1, 2), keepdim=True, unbiased=False)
+        out[c0:c1] = (field - mu) / sd
+    return out
+
+
+def diffusion_coef_torch(logk):
+    """diffusion_coef for one torch field logk [n][n] (any device):
+    [7][N] float64 tensor, same face rule and ordering."""
+    import torch
+    ny, nx = logk.shape
+    k = torch.exp(logk.to(torch.float64))
+    h2 = (1.0 / (nx + 1)) ** 2
+
+    def hm(a, b):
+        return 2.0 * a * b / (a + b)
+
+    kw = torch.empty_like(k); ke = torch.empty_like(k); ks = torch.empty_like(k); kn = torch.empty_like(k)
+    kw[:, 1:] = hm(k[:, 1:], k[:, :-1]); kw[:, 0] = k[:, 0]
+    ke[:, :-1] = hm(k[:, :-1], k[:, 1:]); ke[:, -1] = k[:, -1]
+    ks[1:, :] = hm(k[1:, :], k[:-1, :]); ks[0, :] = k[0, :]
+    kn[:-1, :] = hm(k[:-1, :], k[1:, :]); kn[-1, :] = k[-1, :]
+    coef = torch.zeros((7, nx * ny), dtype=torch.float64, device=logk.device)
+    coef[0] = ((kw + ke + ks + kn) / h2).reshape(-1)
+    coef[1] = (-kw / h2).reshape(-1)
+    coef[2] = (-ke / h2).reshape(-1)
+    coef[3] = (-ks / h2).reshape(-1)
+    coef[4] = (-kn / h2).reshape(-1)
+    return coef
