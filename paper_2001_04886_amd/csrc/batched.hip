@@ -46,8 +46,6 @@ struct BatchSlot {
     double R[513 * 512];   // rotated L G
     double cs[513], sn[513], rhs[513], y[513];
     double T[512 * 17];    // projection coefficients [row][s+1]
-    double coefM[512 * 16];
-    double coefA[513];
     double C[512 * 16];    // Gram output
     GramFactor Wf[128];
     double nu[129], inv_nu[129];
@@ -81,58 +79,221 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 // Phase timer of the owning workgroup: thread 0 reads the constant-rate wall
 // clock after the barrier that closes a phase and charges the interval to one
 // kernel class (matrix powers, Gram, update, residual, scalar work, vector).
+// The accumulators live in LDS (slot SSTEP_K_NCLASS holds the last reading).
 struct PhaseClock {
-    long long t0 = 0;
-    long long acc[SSTEP_K_NCLASS] = {0, 0, 0, 0, 0, 0};
+    long long* acc;  // LDS [SSTEP_K_NCLASS + 1]
     __device__ void start() {
-        if (threadIdx.x == 0) t0 = wall_clock64();
+        if (threadIdx.x == 0) {
+            for (int c = 0; c < SSTEP_K_NCLASS; ++c) acc[c] = 0;
+            acc[SSTEP_K_NCLASS] = wall_clock64();
+        }
     }
     __device__ void lap(int cls) {
         if (threadIdx.x == 0) {
             const long long t = wall_clock64();
-            acc[cls] += t - t0;
-            t0 = t;
+            acc[cls] += t - acc[SSTEP_K_NCLASS];
+            acc[SSTEP_K_NCLASS] = t;
         }
     }
 };
 
-// one stencil level over all points of a system: out = a*(A y) with y = in*sc
-__device__ __forceinline__ double stencil_at(const StencilView& A, const double* in, long long p,
-                                             int i, int j, int l) {
-    const long long sy = A.nx, sz = (long long)A.nx * A.ny;
-    double acc = 0.0;
-    if (i > 0) acc += A.c[1] * in[p - 1];
-    if (i < A.nx - 1) acc += A.c[2] * in[p + 1];
-    if (j > 0) acc += A.c[3] * in[p - sy];
-    if (j < A.ny - 1) acc += A.c[4] * in[p + sy];
-    if (A.ndim == 3) {
-        if (l > 0) acc += A.c[5] * in[p - sz];
-        if (l < A.nz - 1) acc += A.c[6] * in[p + sz];
+typedef double d2v __attribute__((ext_vector_type(2)));
+#define SSTEP_GLOBAL __attribute__((address_space(1)))
+#define SSTEP_LDS __attribute__((address_space(3)))
+
+// explicit address spaces: the basis, x and f live in global memory, the
+// update coefficients in LDS (generic pointers would compile to flat accesses)
+__device__ __forceinline__ d2v ld2(const double* p) { return *(const SSTEP_GLOBAL d2v*)p; }
+__device__ __forceinline__ void st2(double* p, d2v v) { *(SSTEP_GLOBAL d2v*)p = v; }
+__device__ __forceinline__ double ldg(const double* p) { return *(const SSTEP_GLOBAL double*)p; }
+__device__ __forceinline__ double lds(const double* p) { return *(const SSTEP_LDS double*)p; }
+
+// Grid coordinates of the points a thread visits (p = tid, tid + NT, ...),
+// advanced without divisions.
+struct Walker {
+    int i, j, l, di, dj, dl, nx, ny;
+    __device__ Walker(const StencilView& A, long long p0, int step) {
+        nx = A.nx;
+        ny = A.ny;
+        const long long rest = p0 / nx;
+        i = (int)(p0 - rest * nx);
+        j = (int)(rest % ny);
+        l = (int)(rest / ny);
+        const int rows = step / nx;
+        di = step - rows * nx;
+        dj = rows % ny;
+        dl = rows / ny;
     }
-    return acc + A.c[0] * in[p];
+    __device__ __forceinline__ void next() {
+        i += di;
+        j += dj;
+        l += dl;
+        if (i >= nx) {
+            i -= nx;
+            ++j;
+        }
+        if (j >= ny) {
+            j -= ny;
+            ++l;
+        }
+    }
+};
+
+// One stencil pass over the workgroup's points: out = sc * (A in), or with f
+// given r = f - A in into out; returns this thread's share of sum(out^2).
+// Neighbours are summed in the order -x, +x, -y, +y, -z, +z, then the centre
+// (outside the grid = Dirichlet 0).  The
+// operator's scalars are copied to registers first (the descriptor sits in
+// LDS), and constant / per-point coefficients get separate loops.
+template <int NT>
+__device__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
+                             const double* f) {
+    const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz, ndim = Ad.ndim;
+    const long long N = Ad.N, sy = nx, sz = (long long)nx * ny;
+    const double* coef = Ad.coef;
+    double c[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) c[q] = Ad.c[q];
+    const SSTEP_GLOBAL double* gin = (const SSTEP_GLOBAL double*)in;
+    SSTEP_GLOBAL double* gout = (SSTEP_GLOBAL double*)out;
+    const SSTEP_GLOBAL double* gf = (const SSTEP_GLOBAL double*)f;
+    const SSTEP_GLOBAL double* gc = (const SSTEP_GLOBAL double*)coef;
+    StencilView geom;
+    geom.nx = nx;
+    geom.ny = ny;
+    Walker w(geom, threadIdx.x, NT);
+    double sq = 0.0;
+    for (long long p = threadIdx.x; p < N; p += NT, w.next()) {
+        double cc[7];
+        if (coef) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) cc[q] = (q < 2 * ndim + 1) ? gc[q * N + p] : 0.0;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) cc[q] = c[q];
+        }
+        double acc = 0.0;
+        if (w.i > 0) acc += cc[1] * gin[p - 1];
+        if (w.i < nx - 1) acc += cc[2] * gin[p + 1];
+        if (w.j > 0) acc += cc[3] * gin[p - sy];
+        if (w.j < ny - 1) acc += cc[4] * gin[p + sy];
+        if (ndim == 3) {
+            if (w.l > 0) acc += cc[5] * gin[p - sz];
+            if (w.l < nz - 1) acc += cc[6] * gin[p + sz];
+        }
+        acc += cc[0] * gin[p];
+        const double v = f ? gf[p] - acc : sc * acc;
+        gout[p] = v;
+        sq += v * v;
+    }
+    return sq;
 }
 
+// Y[:, l] += sum_{c < nc} V[:, c] M[c * ldm + l] for l < nout <= NMAX (M in LDS);
+// returns this thread's share of ||Y[:, 0]||^2 after the update when norm.
+// Each thread owns point pairs (16-byte loads); eight columns of V are in
+// flight per step; the sum over c runs in column order.  Lanes l >= nout
+// compute on clamped (valid) columns and are never stored, so the loops have
+// no data-dependent branches.
+template <int NT, int NMAX>
+__device__ double wg_lincomb(const double* V, long long ld, int nc, const double* M, int ldm,
+                             double* Y, long long ldy, int nout, long long N, bool norm) {
+    double nacc = 0.0;
+    const long long np = N >> 1;
+    int lc[NMAX];
+#pragma unroll
+    for (int l = 0; l < NMAX; ++l) lc[l] = l < nout ? l : nout - 1;
+    for (long long q = threadIdx.x; q < np; q += NT) {
+        const long long p = 2 * q;
+        d2v a[NMAX];
+#pragma unroll
+        for (int l = 0; l < NMAX; ++l) a[l] = ld2(Y + lc[l] * ldy + p);
+        int c = 0;
+        for (; c + 8 <= nc; c += 8) {
+            d2v v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = ld2(V + (long long)(c + u) * ld + p);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int l = 0; l < NMAX; ++l) {
+                    const double mm = lds(M + (c + u) * ldm + lc[l]);
+                    a[l].x = fma(v[u].x, mm, a[l].x);
+                    a[l].y = fma(v[u].y, mm, a[l].y);
+                }
+        }
+        for (; c < nc; ++c) {
+            const d2v v = ld2(V + (long long)c * ld + p);
+#pragma unroll
+            for (int l = 0; l < NMAX; ++l) {
+                const double mm = lds(M + c * ldm + lc[l]);
+                a[l].x = fma(v.x, mm, a[l].x);
+                a[l].y = fma(v.y, mm, a[l].y);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < NMAX; ++l)
+            if (l < nout) st2(Y + l * ldy + p, a[l]);
+        if (norm) nacc += a[0].x * a[0].x + a[0].y * a[0].y;
+    }
+    if ((N & 1) && threadIdx.x == 0) {
+        const long long p = N - 1;
+        double a[NMAX];
+#pragma unroll
+        for (int l = 0; l < NMAX; ++l) a[l] = ldg(Y + lc[l] * ldy + p);
+        for (int c = 0; c < nc; ++c) {
+            const double v = ldg(V + (long long)c * ld + p);
+#pragma unroll
+            for (int l = 0; l < NMAX; ++l) a[l] = fma(v, lds(M + c * ldm + lc[l]), a[l]);
+        }
+#pragma unroll
+        for (int l = 0; l < NMAX; ++l)
+            if (l < nout) *(SSTEP_GLOBAL double*)(Y + l * ldy + p) = a[l];
+        if (norm) nacc += a[0] * a[0];
+    }
+    return nacc;
+}
+
+// out[a * nz + j] = sum_p X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ): tiles of
+// CA columns of X against all of Z, point pairs per thread, one workgroup
+// reduction per tile.  Columns past ncx / nz are clamped to valid ones and
+// their sums dropped.
 template <int NT, int CA, int KZ>
 __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z, long long ldz,
                         int nz, long long N, double* out /* [ncx][nz] */, double* red) {
-    // tiles of CA columns of X against nz <= KZ columns of Z, reduced per tile
+    const long long np = N >> 1;
+    const double* zc[KZ];
+#pragma unroll
+    for (int j = 0; j < KZ; ++j) zc[j] = Z + (long long)(j < nz ? j : nz - 1) * ldz;
     for (int c0 = 0; c0 < ncx; c0 += CA) {
+        const double* xc[CA];
+#pragma unroll
+        for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : ncx - 1) * ldx;
         double acc[CA][KZ];
 #pragma unroll
         for (int a = 0; a < CA; ++a)
 #pragma unroll
             for (int j = 0; j < KZ; ++j) acc[a][j] = 0.0;
-        for (long long p = threadIdx.x; p < N; p += NT) {
-            double z[KZ];
+        for (long long q = threadIdx.x; q < np; q += NT) {
+            const long long p = 2 * q;
+            d2v z[KZ], x[CA];
 #pragma unroll
-            for (int j = 0; j < KZ; ++j) z[j] = j < nz ? Z[j * ldz + p] : 0.0;
+            for (int j = 0; j < KZ; ++j) z[j] = ld2(zc[j] + p);
+#pragma unroll
+            for (int a = 0; a < CA; ++a) x[a] = ld2(xc[a] + p);
+#pragma unroll
+            for (int a = 0; a < CA; ++a)
+#pragma unroll
+                for (int j = 0; j < KZ; ++j)
+                    acc[a][j] = fma(x[a].y, z[j].y, fma(x[a].x, z[j].x, acc[a][j]));
+        }
+        if ((N & 1) && threadIdx.x == 0) {
+            const long long p = N - 1;
 #pragma unroll
             for (int a = 0; a < CA; ++a) {
-                if (c0 + a < ncx) {
-                    const double xv = X[(long long)(c0 + a) * ldx + p];
+                const double xv = ldg(xc[a] + p);
 #pragma unroll
-                    for (int j = 0; j < KZ; ++j) acc[a][j] = fma(xv, z[j], acc[a][j]);
-                }
+                for (int j = 0; j < KZ; ++j) acc[a][j] = fma(xv, ldg(zc[j] + p), acc[a][j]);
             }
         }
         // workgroup reduction of the CA*KZ sums (wave shuffles, then LDS)
@@ -156,19 +317,93 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
     }
 }
 
+// ---------------------------------------------------------------------------
+// one-thread FP64 scalar steps (kept out of line so that their registers do
+// not weigh on the streaming loops)
+// ---------------------------------------------------------------------------
+
+// Scalar1 of block kb: equilibrated Cholesky of W_k (from the block's own
+// Gram in W.C, start column scaled by inv_nu) and g = W_k^{-1} V_k^T Yhat_s;
+// sh[0..s) = g, sh[s..2s) = N4b coefficients, sh[2 kMaxS] = ||Yhat_s||^2.
+__device__ __noinline__ void scalar_factor(BatchSlot& W, int kb, int s, double rank_tol,
+                                           double* lw, GramFactor* lf, double* sh) {
+    const int s1 = s + 1;
+    const double d0 = W.inv_nu[kb];
+    double* Wk = lw;
+    for (int q = 0; q < s; ++q)
+        for (int pp = 0; pp < s; ++pp)
+            Wk[pp + q * kMaxS] = W.C[pp * s1 + q] * (pp == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
+    gram_factor(Wk, kMaxS, s, rank_tol, lf);
+    const int q = lf->rank;
+    double* g = sh;
+    double* h = sh + 2 * kMaxS + 4;
+    if (q == s) {
+        for (int pp = 0; pp < s; ++pp) h[pp] = W.C[pp * s1 + s] * (pp == 0 ? d0 : 1.0);
+        gram_solve(*lf, h, g);
+        for (int pp = 0; pp < s; ++pp) sh[s + pp] = -g[pp] * (pp == 0 ? d0 : 1.0);
+    } else if (q > 0) {
+        for (int pp = 0; pp < q; ++pp) h[pp] = Wk[pp + q * kMaxS];
+        gram_solve_leading(*lf, q, h, g);
+    }
+    sh[2 * kMaxS] = W.C[s * s1 + s];
+}
+
+// Givens rotations of the q new columns of the L-scaled Hessenberg (the
+// earlier rotations were applied column-parallel already), the rotated rhs,
+// the next start-vector norm and the residual estimate sh[2 kMaxS + 1].
+__device__ __noinline__ void scalar_givens(BatchSlot& W, int kb, int c0, int q, int ldg, double nu,
+                                           double* sh) {
+    for (int j = 0; j < q; ++j) {
+        double* col = W.R + (c0 + j) * ldg;
+        for (int i = c0; i < c0 + j; ++i) {
+            const double x0 = col[i], x1 = col[i + 1];
+            col[i] = W.cs[i] * x0 + W.sn[i] * x1;
+            col[i + 1] = -W.sn[i] * x0 + W.cs[i] * x1;
+        }
+        const int cj = c0 + j;
+        const double x0 = col[cj], x1 = col[cj + 1];
+        double cth = 1.0, sth = 0.0;
+        if (x1 != 0.0) {
+            const double hh = hypot(x0, x1);
+            cth = x0 / hh;
+            sth = x1 / hh;
+        }
+        W.cs[cj] = cth;
+        W.sn[cj] = sth;
+        col[cj] = cth * x0 + sth * x1;
+        col[cj + 1] = 0.0;
+        const double g0 = W.rhs[cj];
+        W.rhs[cj + 1] = -sth * g0;
+        W.rhs[cj] = cth * g0;
+    }
+    W.nu[kb + 1] = nu;
+    W.inv_nu[kb + 1] = nu > 0.0 ? 1.0 / nu : 0.0;
+    sh[2 * kMaxS + 1] = fabs(W.rhs[c0 + q]);
+}
+
+// y = R^{-1} rhs (back substitution) and the assembly coefficients
+// (start columns carry their 1/nu) into lm.
+__device__ __noinline__ void scalar_ysolve(BatchSlot& W, int ncols, int s, int ldg, double* lm) {
+    for (int i = ncols - 1; i >= 0; --i) {
+        double v = W.rhs[i];
+        for (int l = i + 1; l < ncols; ++l) v -= W.R[i + l * ldg] * W.y[l];
+        W.y[i] = v / W.R[i + i * ldg];
+    }
+    for (int c = 0; c < ncols; ++c) lm[c] = W.y[c] * ((c % s == 0) ? W.inv_nu[c / s] : 1.0);
+}
+
 template <int NT, int CA, int KZ>
 __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, double* red,
-                          double* sh, double* lw, GramFactor* lf) {
+                          double* sh, double* lw, GramFactor* lf, double* lm,
+                          const StencilView& A, long long* clk) {
     const int s = args.s, m = args.m, K = m * s, ldg = K + 1, s1 = s + 1;
-    const StencilView A = S.A;
     const long long N = A.N, ld = S.ld;
     double* V = S.ws;
     const int tid = threadIdx.x;
-    const int nx = A.nx, ny = A.ny;
     // Basis change B (monomial): A Y[:,0:s] = Y B with B[j+1][j] = sigma
     const double sigma = S.sigma;
 
-    PhaseClock pc;
+    PhaseClock pc{clk};
     pc.start();
     // ||f||
     double acc = 0.0;
@@ -181,12 +416,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
     for (;;) {
         // r = f - A x into column 0, beta = ||r||
         acc = 0.0;
-        for (long long p = tid; p < N; p += NT) {
-            const int pi = (int)p, i = pi % nx, rest = pi / nx, j = rest % ny, l = rest / ny;
-            const double r = S.f[p] - stencil_at(A, S.x, p, i, j, l);
-            V[p] = r;
-            acc += r * r;
-        }
+        acc = wg_stencil<NT>(A, S.x, V, 1.0, S.f);
         beta = sqrt(wg_sum<NT>(acc, red));
         pc.lap(SSTEP_K_RESID);
         if (!isfinite(beta)) { status = SSTEP_ERR_NONFINITE; break; }
@@ -209,10 +439,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 const double* in = Yk + (long long)(jl - 1) * ld;
                 double* out = Yk + (long long)jl * ld;
                 const double sc = (jl == 1 ? W.inv_nu[kb] : 1.0) / sigma;
-                for (long long p = tid; p < N; p += NT) {
-                    const int pi = (int)p, i = pi % nx, rest = pi / nx, j = rest % ny, l = rest / ny;
-                    out[p] = sc * stencil_at(A, in, p, i, j, l);
-                }
+                (void)wg_stencil<NT>(A, in, out, sc, nullptr);
                 __syncthreads();
             }
             pc.lap(SSTEP_K_MPK);
@@ -229,27 +456,14 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                     gram_solve(W.Wf[i], c, c);
                     for (int q = 0; q < s; ++q) {
                         W.T[(i * s + q) * s1 + l] = c[q];
-                        W.coefM[(i * s + q) * s + (l - 1)] = -c[q] * (q == 0 ? W.inv_nu[i] : 1.0);
+                        lm[(i * s + q) * s + (l - 1)] = -c[q] * (q == 0 ? W.inv_nu[i] : 1.0);
                         if (l == 1) W.T[(i * s + q) * s1] = 0.0;
                     }
                 }
                 __syncthreads();
                 pc.lap(SSTEP_K_SCALAR);
-                // y_j -= sum_c V_c coefM[c][j]
-                for (long long p = tid; p < N; p += NT) {
-                    double a[KZ];
-#pragma unroll
-                    for (int l = 0; l < KZ; ++l) a[l] = l < s ? Yk[(long long)(l + 1) * ld + p] : 0.0;
-                    for (int cc = 0; cc < c0; ++cc) {
-                        const double v = V[(long long)cc * ld + p];
-#pragma unroll
-                        for (int l = 0; l < KZ; ++l)
-                            if (l < s) a[l] = fma(v, W.coefM[cc * s + l], a[l]);
-                    }
-#pragma unroll
-                    for (int l = 0; l < KZ; ++l)
-                        if (l < s) Yk[(long long)(l + 1) * ld + p] = a[l];
-                }
+                // y_j -= sum_c V_c coefM[c][j]  (coefficients in LDS)
+                wg_lincomb<NT, KZ>(V, ld, c0, lm, s, Yk + ld, ld, s, N, false);
                 __syncthreads();
                 pc.lap(SSTEP_K_UPDATE);
             }
@@ -257,27 +471,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
             wg_gram<NT, CA, KZ + 1>(Yk, ld, s1, Yk, ld, s1, N, W.C, red);
             pc.lap(SSTEP_K_GRAM);
             // Scalar1: factor W_k in LDS (one thread), copy the factor out
-            if (tid == 0) {
-                const double d0 = W.inv_nu[kb];
-                double* Wk = lw;
-                for (int q = 0; q < s; ++q)
-                    for (int pp = 0; pp < s; ++pp)
-                        Wk[pp + q * kMaxS] =
-                            W.C[pp * s1 + q] * (pp == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
-                gram_factor(Wk, kMaxS, s, args.rank_tol, lf);
-                const int q = lf->rank;
-                double* g = sh;  // g[0..s), coefN4b[s..2s), scalars at sh[2 kMaxS ..]
-                double* h = sh + 2 * kMaxS + 4;
-                if (q == s) {
-                    for (int pp = 0; pp < s; ++pp) h[pp] = W.C[pp * s1 + s] * (pp == 0 ? d0 : 1.0);
-                    gram_solve(*lf, h, g);
-                    for (int pp = 0; pp < s; ++pp) sh[s + pp] = -g[pp] * (pp == 0 ? d0 : 1.0);
-                } else if (q > 0) {
-                    for (int pp = 0; pp < q; ++pp) h[pp] = Wk[pp + q * kMaxS];
-                    gram_solve_leading(*lf, q, h, g);
-                }
-                sh[2 * kMaxS] = W.C[s * s1 + s];  // ||Yhat_s||^2
-            }
+            if (tid == 0) scalar_factor(W, kb, s, args.rank_tol, lw, lf, sh);
             __syncthreads();
             {
                 const double* src = reinterpret_cast<const double*>(lf);
@@ -292,15 +486,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
             if (q == s) {
                 // w_hat = Yhat_s - V_k g, nu^2
                 double* ys = Yk + (long long)s * ld;
-                acc = 0.0;
-                for (long long p = tid; p < N; p += NT) {
-                    double v = ys[p];
-#pragma unroll
-                    for (int l = 0; l < KZ; ++l)
-                        if (l < s) v = fma(Yk[(long long)l * ld + p], sh[s + l], v);
-                    ys[p] = v;
-                    acc += v * v;
-                }
+                acc = wg_lincomb<NT, 1>(Yk, ld, s, sh + s, 1, ys, ld, 1, N, true);
                 nu = sqrt(wg_sum<NT>(acc, red));
             }
             pc.lap(SSTEP_K_VEC);
@@ -351,34 +537,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 col[c0] = x0;
             }
             __syncthreads();
-            if (tid == 0) {
-                for (int j = 0; j < q; ++j) {
-                    double* col = W.R + (c0 + j) * ldg;
-                    for (int i = c0; i < c0 + j; ++i) {
-                        const double x0 = col[i], x1 = col[i + 1];
-                        col[i] = W.cs[i] * x0 + W.sn[i] * x1;
-                        col[i + 1] = -W.sn[i] * x0 + W.cs[i] * x1;
-                    }
-                    const int cj = c0 + j;
-                    const double x0 = col[cj], x1 = col[cj + 1];
-                    double cth = 1.0, sth = 0.0;
-                    if (x1 != 0.0) {
-                        const double hh = hypot(x0, x1);
-                        cth = x0 / hh;
-                        sth = x1 / hh;
-                    }
-                    W.cs[cj] = cth;
-                    W.sn[cj] = sth;
-                    col[cj] = cth * x0 + sth * x1;
-                    col[cj + 1] = 0.0;
-                    const double g0 = W.rhs[cj];
-                    W.rhs[cj + 1] = -sth * g0;
-                    W.rhs[cj] = cth * g0;
-                }
-                W.nu[kb + 1] = nu;
-                W.inv_nu[kb + 1] = nu > 0.0 ? 1.0 / nu : 0.0;
-                sh[2 * kMaxS + 1] = fabs(W.rhs[c0 + q]);
-            }
+            if (tid == 0) scalar_givens(W, kb, c0, q, ldg, nu, sh);
             __syncthreads();
             pc.lap(SSTEP_K_SCALAR);
             ncols = c0 + q;
@@ -389,20 +548,9 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
         }
         if (err) { status = SSTEP_ERR_NONFINITE; break; }
         // y = R^{-1} rhs, assembly coefficients
-        if (tid == 0) {
-            for (int i = ncols - 1; i >= 0; --i) {
-                double v = W.rhs[i];
-                for (int l = i + 1; l < ncols; ++l) v -= W.R[i + l * ldg] * W.y[l];
-                W.y[i] = v / W.R[i + i * ldg];
-            }
-            for (int c = 0; c < ncols; ++c) W.coefA[c] = W.y[c] * ((c % s == 0) ? W.inv_nu[c / s] : 1.0);
-        }
+        if (tid == 0) scalar_ysolve(W, ncols, s, ldg, lm);
         __syncthreads();
-        for (long long p = tid; p < N; p += NT) {
-            double v = S.x[p];
-            for (int c = 0; c < ncols; ++c) v = fma(V[(long long)c * ld + p], W.coefA[c], v);
-            S.x[p] = v;
-        }
+        wg_lincomb<NT, 1>(V, ld, ncols, lm, 1, S.x, N, 1, N, false);
         __syncthreads();
         pc.lap(SSTEP_K_UPDATE);
     }
@@ -422,6 +570,9 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
     __shared__ double sh[3 * kMaxS + 4];
     __shared__ double lw[kMaxS * kMaxS];
     __shared__ GramFactor lf;
+    __shared__ double lm[512 * 8];  // update / assembly coefficients
+    __shared__ StencilView sA;      // the current system's operator
+    __shared__ long long clk[SSTEP_K_NCLASS + 1];
     __shared__ int next;
     BatchSlot& W = args.slots[blockIdx.x];
     for (;;) {
@@ -430,7 +581,10 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
         const int k = next;
         __syncthreads();
         if (k >= args.nsys) break;
-        solve_one<NT, CA, KZ>(args, args.sys[args.order[k]], W, red, sh, lw, &lf);
+        BatchSys& S = args.sys[args.order[k]];
+        if (threadIdx.x == 0) sA = S.A;
+        __syncthreads();
+        solve_one<NT, CA, KZ>(args, S, W, red, sh, lw, &lf, lm, sA, clk);
     }
 }
 
@@ -541,9 +695,9 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
             b.x = x[i];
             b.ld = col_stride(b.A.N);
             b.ws = (double*)take((size_t)(m * s + 1) * b.ld * sizeof(double));
-            double g = 0.0;
-            for (int q = 0; q < 2 * A[i].ndim + 1; ++q) g += std::fabs(A[i].c[q]);
-            b.sigma = opt.sigma > 0 ? opt.sigma : pow2_ceil(g);
+            // sigma: power-of-two Gershgorin bound (per-point coefficients are
+            // scanned on the device; the queue word is free scratch until launch)
+            b.sigma = op_params(A[i], opt.sigma, P->st, (double*)queue).sigma;
         }
         std::vector<int> order(nsys);
         std::iota(order.begin(), order.end(), 0);

@@ -188,7 +188,8 @@ static int batch_args_ok(int nsys, const sstep_stencil* A, const double* const* 
         if (opt->batch_wgs_per_cu < 0 || opt->batch_wgs_per_cu > 4) return 0;
     }
     for (int i = 0; i < nsys; ++i) {
-        if (!stencil_ok(&A[i]) || A[i].coef || !f[i] || !x[i]) return 0;
+        if (!stencil_ok(&A[i]) || !f[i] || !x[i]) return 0;
+        if (((uintptr_t)f[i] & 15) || ((uintptr_t)x[i] & 15) || ((uintptr_t)A[i].coef & 15)) return 0;
         if (grid_points(A[i]) > (1LL << 30)) return 0;
     }
     return 1;
