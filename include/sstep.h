@@ -84,11 +84,12 @@ typedef struct {
     size_t workspace_bytes;
     void *stream;         /* hipStream_t                                                   */
     /* batched solver only (sstep_batch_plan_create): launch shape of the
-       persistent kernel; 0 = defaults (512 threads, 1 workgroup per CU) */
+       persistent kernel; 0 = defaults (512 threads, 1 workgroup per CU, no teams) */
     int32_t batch_threads;     /* 256, 512 or 1024 threads per workgroup               */
     int32_t batch_wgs_per_cu;  /* resident workgroups per compute unit (1..4)          */
     int32_t batch_graph;       /* 1: capture the launch in a hipGraph, replay it       */
-    int32_t reserved;
+    int32_t batch_team;        /* 1, 2, 4 or 8 workgroups solving one large system
+                                  together (systems of >= 16384 points per member)   */
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */

@@ -1,17 +1,24 @@
 // batched.hip -- many independent s-step GMRES(m) solves (Sec. 4, Alg. 4.2)
 // in one persistent launch.
 //
-// The grid holds as many workgroups as can be resident at once.  Each
-// workgroup repeatedly takes the next system from a global queue (systems are
-// ordered largest first) and runs the whole restarted s-step GMRES for it:
-// matrix powers level by level, the Gram of the new block against the stored
-// blocks, the block update, the block's own Gram, the FP64 Cholesky /
-// Hessenberg / Givens work, the next start vector, the assembly of x and the
-// true residual.  A workgroup only ever waits on its own barrier, so the launch
-// cannot deadlock whatever the residency; every system solve is bounded by the
-// block cap, so every workgroup reaches the end of the queue.
+// The grid holds exactly as many workgroups as can be resident at once.
+// Systems are split by size into two queues, each ordered largest first:
+//   * phase 1 (teams): workgroups are grouped in teams of T (members share an
+//     XCD).  A team takes the next large system and solves it cooperatively:
+//     each member owns a contiguous range of grid rows of every vector; the
+//     partial sums of every reduction are published per member and summed in
+//     rank order after a team barrier, so each member holds bit-identical
+//     totals and repeats the small FP64 work itself; matrix-powers levels and
+//     the assembly are separated by team barriers because the stencil reads
+//     rows of neighbouring members;
+//   * phase 2: every workgroup takes the next small system alone.
+// Team barriers are counters advanced with agent-scope release/acquire
+// atomics (the L2 of each XCD is written back / invalidated), with a bounded
+// spin: on a time-out the launch is aborted and the affected systems report
+// SSTEP_ERR_HIP.  The grid size is checked against the occupancy of the
+// kernel, so every member of a team is resident.
 //
-// The arithmetic per block is the same as in gmres.hip (normalised start
+// Per block the arithmetic is the same as in gmres.hip (normalised start
 // vectors with their norms folded into coefficients, one-pass block CGS, a
 // direct W_k, equilibrated Cholesky with rank truncation, L-scaled Givens QR).
 #include <hip/hip_runtime.h>
@@ -28,6 +35,9 @@
 
 namespace sstep {
 
+constexpr int kMaxTeam = 8;
+constexpr int kPartLen = 512 * 8 + 64;  // largest reduction: c0 * s (Gram) + scalars
+
 struct BatchSys {
     StencilView A;
     const double* f;
@@ -35,9 +45,9 @@ struct BatchSys {
     double* ws;        // this system's basis region: (m*s+1) columns of ld doubles
     long long ld;
     double sigma;
-    int status, blocks, cycles, pad;
+    int status, blocks, cycles, team;
     double rel_resid;
-    long long ticks[SSTEP_K_NCLASS];  // wall-clock ticks of the owning workgroup per class
+    long long ticks[SSTEP_K_NCLASS];  // wall-clock ticks of the (lead) workgroup per class
 };
 
 // per-workgroup scratch for the small dense state (sized for m*s <= 512)
@@ -46,21 +56,37 @@ struct BatchSlot {
     double R[513 * 512];   // rotated L G
     double cs[513], sn[513], rhs[513], y[513];
     double T[512 * 17];    // projection coefficients [row][s+1]
-    double C[512 * 16];    // Gram output
+    double C[512 * 16];    // Gram (team total)
+    double part[2][kPartLen];  // this workgroup's partial sums, double-buffered
     GramFactor Wf[128];
     double nu[129], inv_nu[129];
 };
 
 struct BatchArgs {
     BatchSys* sys;
-    const int* order;
-    int nsys;
+    const int* order_big;    // solved by teams, largest first
+    const int* order_small;  // solved by one workgroup each, largest first
+    int nbig, nsmall;
     int s, m;
     double tol;
     int max_blocks;
     double rank_tol, lucky_tol;
     BatchSlot* slots;
-    int* queue;
+    int* queue;              // [0] big-system queue, [1] small-system queue, [2] abort flag
+    unsigned* team_sync;     // per team 64 words: [0] barrier counter, [32] mailbox
+    int team;                // workgroups per team (1: no phase 1)
+    long long spin_limit;
+};
+
+// A workgroup's team (kept in LDS).  T == 1: the workgroup alone.
+struct Team {
+    int T, rank, parity, failed;
+    unsigned target;
+    unsigned* cnt;
+    int* mailbox;
+    int* abort;
+    long long limit;
+    BatchSlot* member[kMaxTeam];
 };
 
 template <int NT>
@@ -76,12 +102,73 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     return t;
 }
 
-// Phase timer of the owning workgroup: thread 0 reads the constant-rate wall
+// Team barrier: every member's global writes before it are visible to every
+// member after it.  Returns false (and marks the team failed) on a time-out or
+// an abort raised elsewhere; later barriers then return at once.
+__device__ bool team_barrier(Team& tm) {
+    if (tm.T == 1) {
+        __syncthreads();
+        return true;
+    }
+    // every wave publishes its own stores (agent-scope release: wait for them
+    // and write the XCD's L2 back); __syncthreads alone does not wait for them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0 && !tm.failed) {
+        tm.target += tm.T;
+        __hip_atomic_fetch_add(tm.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long long spins = 0;
+        while (__hip_atomic_load(tm.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tm.target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > tm.limit ||
+                __hip_atomic_load(tm.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                tm.failed = 1;
+                __hip_atomic_store(tm.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return !tm.failed;
+}
+
+// out[0..n) = sum over members (rank order) of their part[parity][0..n); each
+// member first wrote its own partials there.  T == 1: out = own partials.
+template <int NT>
+__device__ void team_combine(Team& tm, BatchSlot& W, int n, double* out) {
+    const int buf = tm.parity;
+    if (tm.T == 1) {
+        if (out != W.part[buf])
+            for (int i = threadIdx.x; i < n; i += NT) out[i] = W.part[buf][i];
+        __syncthreads();
+        return;
+    }
+    team_barrier(tm);
+    for (int i = threadIdx.x; i < n; i += NT) {
+        double t = 0.0;
+        for (int r = 0; r < tm.T; ++r) t += tm.member[r]->part[buf][i];
+        out[i] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tm.parity ^= 1;
+    __syncthreads();
+}
+
+// a scalar reduction over the team: v is this workgroup's total
+template <int NT>
+__device__ double team_scalar(Team& tm, BatchSlot& W, double v, double* lds1) {
+    if (tm.T == 1) return v;
+    if (threadIdx.x == 0) W.part[tm.parity][0] = v;
+    team_combine<NT>(tm, W, 1, lds1);
+    return lds1[0];
+}
+
+// Phase timer of the (lead) workgroup: thread 0 reads the constant-rate wall
 // clock after the barrier that closes a phase and charges the interval to one
-// kernel class (matrix powers, Gram, update, residual, scalar work, vector).
-// The accumulators live in LDS (slot SSTEP_K_NCLASS holds the last reading).
+// kernel class.  Accumulators in LDS (slot SSTEP_K_NCLASS: last reading).
 struct PhaseClock {
-    long long* acc;  // LDS [SSTEP_K_NCLASS + 1]
+    long long* acc;
     __device__ void start() {
         if (threadIdx.x == 0) {
             for (int c = 0; c < SSTEP_K_NCLASS; ++c) acc[c] = 0;
@@ -106,15 +193,29 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ d2v ld2(const double* p) { return *(const SSTEP_GLOBAL d2v*)p; }
 __device__ __forceinline__ void st2(double* p, d2v v) { *(SSTEP_GLOBAL d2v*)p = v; }
 __device__ __forceinline__ double ldg(const double* p) { return *(const SSTEP_GLOBAL double*)p; }
+__device__ __forceinline__ void stg(double* p, double v) { *(SSTEP_GLOBAL double*)p = v; }
 __device__ __forceinline__ double lds(const double* p) { return *(const SSTEP_LDS double*)p; }
 
-// Grid coordinates of the points a thread visits (p = tid, tid + NT, ...),
+// Point range [P0, P1) of a workgroup: pairs [pa, pb) with even ends (16-byte
+// loads) and at most two single points (e0 at the front, e1 at the back).
+struct Range {
+    long long P0, P1, pa, pb, e0, e1;
+    __device__ Range(long long p0, long long p1) : P0(p0), P1(p1) {
+        pa = (p0 + 1) & ~1LL;
+        pb = p1 & ~1LL;
+        if (pb < pa) pb = pa;
+        e0 = (p0 < pa && p0 < p1) ? p0 : -1;
+        e1 = (pb < p1 && pb >= pa) ? pb : -1;
+    }
+};
+
+// Grid coordinates of the points a thread visits (p = p0, p0 + step, ...),
 // advanced without divisions.
 struct Walker {
     int i, j, l, di, dj, dl, nx, ny;
-    __device__ Walker(const StencilView& A, long long p0, int step) {
-        nx = A.nx;
-        ny = A.ny;
+    __device__ Walker(int nx_, int ny_, long long p0, int step) {
+        nx = nx_;
+        ny = ny_;
         const long long rest = p0 / nx;
         i = (int)(p0 - rest * nx);
         j = (int)(rest % ny);
@@ -139,15 +240,14 @@ struct Walker {
     }
 };
 
-// One stencil pass over the workgroup's points: out = sc * (A in), or with f
-// given r = f - A in into out; returns this thread's share of sum(out^2).
+// One stencil pass over points [P0, P1): out = sc * (A in), or with f given
+// r = f - A in into out; returns this thread's share of sum(out^2).
 // Neighbours are summed in the order -x, +x, -y, +y, -z, +z, then the centre
-// (outside the grid = Dirichlet 0).  The
-// operator's scalars are copied to registers first (the descriptor sits in
-// LDS), and constant / per-point coefficients get separate loops.
+// (outside the grid = Dirichlet 0).  The operator's scalars are copied to
+// registers first (the descriptor sits in LDS).
 template <int NT>
 __device__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
-                             const double* f) {
+                             const double* f, long long P0, long long P1) {
     const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz, ndim = Ad.ndim;
     const long long N = Ad.N, sy = nx, sz = (long long)nx * ny;
     const double* coef = Ad.coef;
@@ -158,12 +258,9 @@ __device__ double wg_stencil(const StencilView& Ad, const double* in, double* ou
     SSTEP_GLOBAL double* gout = (SSTEP_GLOBAL double*)out;
     const SSTEP_GLOBAL double* gf = (const SSTEP_GLOBAL double*)f;
     const SSTEP_GLOBAL double* gc = (const SSTEP_GLOBAL double*)coef;
-    StencilView geom;
-    geom.nx = nx;
-    geom.ny = ny;
-    Walker w(geom, threadIdx.x, NT);
+    Walker w(nx, ny, P0 + threadIdx.x, NT);
     double sq = 0.0;
-    for (long long p = threadIdx.x; p < N; p += NT, w.next()) {
+    for (long long p = P0 + threadIdx.x; p < P1; p += NT, w.next()) {
         double cc[7];
         if (coef) {
 #pragma unroll
@@ -189,22 +286,20 @@ __device__ double wg_stencil(const StencilView& Ad, const double* in, double* ou
     return sq;
 }
 
-// Y[:, l] += sum_{c < nc} V[:, c] M[c * ldm + l] for l < nout <= NMAX (M in LDS);
-// returns this thread's share of ||Y[:, 0]||^2 after the update when norm.
-// Each thread owns point pairs (16-byte loads); eight columns of V are in
-// flight per step; the sum over c runs in column order.  Lanes l >= nout
-// compute on clamped (valid) columns and are never stored, so the loops have
-// no data-dependent branches.
+// Y[:, l] += sum_{c < nc} V[:, c] M[c * ldm + l] for l < nout <= NMAX (M in LDS)
+// over the points of R; returns this thread's share of ||Y[:, 0]||^2 after the
+// update when norm.  Threads own point pairs (16-byte loads); eight columns of
+// V are in flight per step; the sum over c runs in column order.  Lanes
+// l >= nout compute on clamped (valid) columns and are never stored, so the
+// loops have no data-dependent branches.
 template <int NT, int NMAX>
 __device__ double wg_lincomb(const double* V, long long ld, int nc, const double* M, int ldm,
-                             double* Y, long long ldy, int nout, long long N, bool norm) {
+                             double* Y, long long ldy, int nout, const Range& R, bool norm) {
     double nacc = 0.0;
-    const long long np = N >> 1;
     int lc[NMAX];
 #pragma unroll
     for (int l = 0; l < NMAX; ++l) lc[l] = l < nout ? l : nout - 1;
-    for (long long q = threadIdx.x; q < np; q += NT) {
-        const long long p = 2 * q;
+    for (long long p = R.pa + 2 * threadIdx.x; p < R.pb; p += 2 * NT) {
         d2v a[NMAX];
 #pragma unroll
         for (int l = 0; l < NMAX; ++l) a[l] = ld2(Y + lc[l] * ldy + p);
@@ -236,35 +331,36 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
             if (l < nout) st2(Y + l * ldy + p, a[l]);
         if (norm) nacc += a[0].x * a[0].x + a[0].y * a[0].y;
     }
-    if ((N & 1) && threadIdx.x == 0) {
-        const long long p = N - 1;
+    // the (at most two) single points of the range
+    const long long pe = threadIdx.x == 0 ? R.e0 : (threadIdx.x == 1 ? R.e1 : -1);
+    if (pe >= 0) {
         double a[NMAX];
 #pragma unroll
-        for (int l = 0; l < NMAX; ++l) a[l] = ldg(Y + lc[l] * ldy + p);
+        for (int l = 0; l < NMAX; ++l) a[l] = ldg(Y + lc[l] * ldy + pe);
         for (int c = 0; c < nc; ++c) {
-            const double v = ldg(V + (long long)c * ld + p);
+            const double v = ldg(V + (long long)c * ld + pe);
 #pragma unroll
             for (int l = 0; l < NMAX; ++l) a[l] = fma(v, lds(M + c * ldm + lc[l]), a[l]);
         }
 #pragma unroll
         for (int l = 0; l < NMAX; ++l)
-            if (l < nout) *(SSTEP_GLOBAL double*)(Y + l * ldy + p) = a[l];
+            if (l < nout) stg(Y + l * ldy + pe, a[l]);
         if (norm) nacc += a[0] * a[0];
     }
     return nacc;
 }
 
-// out[a * nz + j] = sum_p X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ): tiles of
-// CA columns of X against all of Z, point pairs per thread, one workgroup
-// reduction per tile.  Columns past ncx / nz are clamped to valid ones and
-// their sums dropped.
+// out[a * nz + j] = sum_{p in R} X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ):
+// tiles of CA columns of X against all of Z, point pairs per thread, one
+// workgroup reduction per tile.  Columns past ncx / nz are clamped to valid
+// ones and their sums dropped.
 template <int NT, int CA, int KZ>
 __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z, long long ldz,
-                        int nz, long long N, double* out /* [ncx][nz] */, double* red) {
-    const long long np = N >> 1;
+                        int nz, const Range& R, double* out /* [ncx][nz] */, double* red) {
     const double* zc[KZ];
 #pragma unroll
     for (int j = 0; j < KZ; ++j) zc[j] = Z + (long long)(j < nz ? j : nz - 1) * ldz;
+    const long long pe = threadIdx.x == 0 ? R.e0 : (threadIdx.x == 1 ? R.e1 : -1);
     for (int c0 = 0; c0 < ncx; c0 += CA) {
         const double* xc[CA];
 #pragma unroll
@@ -274,8 +370,7 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
         for (int a = 0; a < CA; ++a)
 #pragma unroll
             for (int j = 0; j < KZ; ++j) acc[a][j] = 0.0;
-        for (long long q = threadIdx.x; q < np; q += NT) {
-            const long long p = 2 * q;
+        for (long long p = R.pa + 2 * threadIdx.x; p < R.pb; p += 2 * NT) {
             d2v z[KZ], x[CA];
 #pragma unroll
             for (int j = 0; j < KZ; ++j) z[j] = ld2(zc[j] + p);
@@ -287,13 +382,12 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
                 for (int j = 0; j < KZ; ++j)
                     acc[a][j] = fma(x[a].y, z[j].y, fma(x[a].x, z[j].x, acc[a][j]));
         }
-        if ((N & 1) && threadIdx.x == 0) {
-            const long long p = N - 1;
+        if (pe >= 0) {
 #pragma unroll
             for (int a = 0; a < CA; ++a) {
-                const double xv = ldg(xc[a] + p);
+                const double xv = ldg(xc[a] + pe);
 #pragma unroll
-                for (int j = 0; j < KZ; ++j) acc[a][j] = fma(xv, ldg(zc[j] + p), acc[a][j]);
+                for (int j = 0; j < KZ; ++j) acc[a][j] = fma(xv, ldg(zc[j] + pe), acc[a][j]);
             }
         }
         // workgroup reduction of the CA*KZ sums (wave shuffles, then LDS)
@@ -392,33 +486,53 @@ __device__ __noinline__ void scalar_ysolve(BatchSlot& W, int ncols, int s, int l
     for (int c = 0; c < ncols; ++c) lm[c] = W.y[c] * ((c % s == 0) ? W.inv_nu[c / s] : 1.0);
 }
 
+// LDS state of a workgroup handed to the solve.
+struct WgShared {
+    double* red;
+    double* sh;
+    double* lw;
+    GramFactor* lf;
+    double* lm;
+    double* l1;
+    long long* clk;
+};
+
+// The whole restarted s-step GMRES for one system, by a team (T >= 1).
 template <int NT, int CA, int KZ>
-__device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, double* red,
-                          double* sh, double* lw, GramFactor* lf, double* lm,
-                          const StencilView& A, long long* clk) {
-    const int s = args.s, m = args.m, K = m * s, ldg = K + 1, s1 = s + 1;
+__device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, const WgShared& L,
+                          const StencilView& A, Team& tm) {
+    const int s = args.s, m = args.m, K = m * s, ldg_ = K + 1, s1 = s + 1;
     const long long N = A.N, ld = S.ld;
     double* V = S.ws;
     const int tid = threadIdx.x;
-    // Basis change B (monomial): A Y[:,0:s] = Y B with B[j+1][j] = sigma
     const double sigma = S.sigma;
+    // this member's rows of the grid
+    const long long rows = (long long)A.ny * A.nz;
+    const long long r0 = rows * tm.rank / tm.T, r1 = rows * (tm.rank + 1) / tm.T;
+    const Range R(r0 * A.nx, r1 * A.nx);
+    double* red = L.red;
+    double* sh = L.sh;
+    double* lm = L.lm;
 
-    PhaseClock pc{clk};
+    PhaseClock pc{L.clk};
     pc.start();
     // ||f||
     double acc = 0.0;
-    for (long long p = tid; p < N; p += NT) acc += S.f[p] * S.f[p];
-    const double fnorm = sqrt(wg_sum<NT>(acc, red));
+    for (long long p = R.P0 + tid; p < R.P1; p += NT) {
+        const double v = ldg(S.f + p);
+        acc += v * v;
+    }
+    const double fnorm = sqrt(team_scalar<NT>(tm, W, wg_sum<NT>(acc, red), L.l1));
     pc.lap(SSTEP_K_VEC);
     const double tol_abs = args.tol * fnorm;
     int blocks = 0, cycles = 0, status = SSTEP_NOT_CONVERGED;
     double beta = 0.0;
     for (;;) {
         // r = f - A x into column 0, beta = ||r||
-        acc = 0.0;
-        acc = wg_stencil<NT>(A, S.x, V, 1.0, S.f);
-        beta = sqrt(wg_sum<NT>(acc, red));
+        acc = wg_stencil<NT>(A, S.x, V, 1.0, S.f, R.P0, R.P1);
+        beta = sqrt(team_scalar<NT>(tm, W, wg_sum<NT>(acc, red), L.l1));
         pc.lap(SSTEP_K_RESID);
+        if (tm.failed) { status = SSTEP_ERR_HIP; break; }
         if (!isfinite(beta)) { status = SSTEP_ERR_NONFINITE; break; }
         if (beta <= tol_abs) { status = SSTEP_OK; break; }
         if (blocks >= args.max_blocks) { status = SSTEP_NOT_CONVERGED; break; }
@@ -434,18 +548,21 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
         for (int kb = 0; kb < m && blocks < args.max_blocks; ++kb) {
             const int c0 = kb * s;
             double* Yk = V + (long long)c0 * ld;
-            // matrix powers: y_j = A y_{j-1} / sigma, y_0 = stored column * inv_nu
+            // matrix powers: y_j = A y_{j-1} / sigma, y_0 = stored column * inv_nu;
+            // the next level reads neighbouring members' rows
             for (int jl = 1; jl <= s; ++jl) {
                 const double* in = Yk + (long long)(jl - 1) * ld;
                 double* out = Yk + (long long)jl * ld;
                 const double sc = (jl == 1 ? W.inv_nu[kb] : 1.0) / sigma;
-                (void)wg_stencil<NT>(A, in, out, sc, nullptr);
-                __syncthreads();
+                (void)wg_stencil<NT>(A, in, out, sc, nullptr, R.P0, R.P1);
+                team_barrier(tm);
             }
             pc.lap(SSTEP_K_MPK);
             if (kb > 0) {
                 // C = V_prev^T [y_1..y_s]
-                wg_gram<NT, CA, KZ>(V, ld, c0, Yk + ld, ld, s, N, W.C, red);
+                double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
+                wg_gram<NT, CA, KZ>(V, ld, c0, Yk + ld, ld, s, R, gout, red);
+                if (tm.T > 1) team_combine<NT>(tm, W, c0 * s, W.C);
                 pc.lap(SSTEP_K_GRAM);
                 // T_i = W_i^{-1} C_i, update coefficients
                 for (int idx = tid; idx < kb * s; idx += NT) {
@@ -462,32 +579,35 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 }
                 __syncthreads();
                 pc.lap(SSTEP_K_SCALAR);
-                // y_j -= sum_c V_c coefM[c][j]  (coefficients in LDS)
-                wg_lincomb<NT, KZ>(V, ld, c0, lm, s, Yk + ld, ld, s, N, false);
+                // y_j -= sum_c V_c coefM[c][j]  (coefficients in LDS, own rows only)
+                wg_lincomb<NT, KZ>(V, ld, c0, lm, s, Yk + ld, ld, s, R, false);
                 __syncthreads();
                 pc.lap(SSTEP_K_UPDATE);
             }
             // block Gram of [w_k, y_1..y_s]
-            wg_gram<NT, CA, KZ + 1>(Yk, ld, s1, Yk, ld, s1, N, W.C, red);
+            {
+                double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
+                wg_gram<NT, CA, KZ + 1>(Yk, ld, s1, Yk, ld, s1, R, gout, red);
+                if (tm.T > 1) team_combine<NT>(tm, W, s1 * s1, W.C);
+            }
             pc.lap(SSTEP_K_GRAM);
-            // Scalar1: factor W_k in LDS (one thread), copy the factor out
-            if (tid == 0) scalar_factor(W, kb, s, args.rank_tol, lw, lf, sh);
+            if (tid == 0) scalar_factor(W, kb, s, args.rank_tol, L.lw, L.lf, sh);
             __syncthreads();
             {
-                const double* src = reinterpret_cast<const double*>(lf);
+                const double* src = reinterpret_cast<const double*>(L.lf);
                 double* dst = reinterpret_cast<double*>(&W.Wf[kb]);
                 for (int i = tid; i < (int)(sizeof(GramFactor) / sizeof(double)); i += NT) dst[i] = src[i];
             }
             __syncthreads();
             pc.lap(SSTEP_K_SCALAR);
             const int q = W.Wf[kb].rank;
-            if (q == 0) { err = true; break; }
+            if (q == 0 || tm.failed) { err = true; break; }
             double nu = 0.0;
             if (q == s) {
-                // w_hat = Yhat_s - V_k g, nu^2
+                // w_hat = Yhat_s - V_k g, nu^2 (the next matrix powers read it)
                 double* ys = Yk + (long long)s * ld;
-                acc = wg_lincomb<NT, 1>(Yk, ld, s, sh + s, 1, ys, ld, 1, N, true);
-                nu = sqrt(wg_sum<NT>(acc, red));
+                acc = wg_lincomb<NT, 1>(Yk, ld, s, sh + s, 1, ys, ld, 1, R, true);
+                nu = sqrt(team_scalar<NT>(tm, W, wg_sum<NT>(acc, red), L.l1));
             }
             pc.lap(SSTEP_K_VEC);
             const bool lucky = (q == s) && !(nu > args.lucky_tol * sqrt(sh[2 * kMaxS]));
@@ -505,15 +625,15 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 if (r <= c0) {
                     for (int cp = (r > 0 ? r - 1 : 0); cp < c0; ++cp) {
                         const double t = W.T[cp * s1 + j];
-                        if (t != 0.0) val -= W.G[r + cp * ldg] * t;
+                        if (t != 0.0) val -= W.G[r + cp * ldg_] * t;
                     }
                 }
-                W.G[r + (c0 + j) * ldg] = val;
+                W.G[r + (c0 + j) * ldg_] = val;
             }
             __syncthreads();
             for (int idx = tid; idx < q * (c0 + q + 1); idx += NT) {
                 const int j = idx / (c0 + q + 1), r = idx % (c0 + q + 1);
-                const double* gc = W.G + (c0 + j) * ldg;
+                const double* gc = W.G + (c0 + j) * ldg_;
                 double val;
                 if (r == c0 + q) {
                     val = gc[r];
@@ -523,11 +643,11 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                     val = 0.0;
                     for (int b = pp; b < qi; ++b) val += gram_L(W.Wf[i], pp, b) * gc[i * s + b];
                 }
-                W.R[r + (c0 + j) * ldg] = val;
+                W.R[r + (c0 + j) * ldg_] = val;
             }
             __syncthreads();
             if (tid < q) {
-                double* col = W.R + (c0 + tid) * ldg;
+                double* col = W.R + (c0 + tid) * ldg_;
                 double x0 = col[0];
                 for (int i = 0; i < c0; ++i) {
                     const double cth = W.cs[i], sth = W.sn[i], x1 = col[i + 1];
@@ -537,7 +657,7 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
                 col[c0] = x0;
             }
             __syncthreads();
-            if (tid == 0) scalar_givens(W, kb, c0, q, ldg, nu, sh);
+            if (tid == 0) scalar_givens(W, kb, c0, q, ldg_, nu, sh);
             __syncthreads();
             pc.lap(SSTEP_K_SCALAR);
             ncols = c0 + q;
@@ -546,20 +666,22 @@ __device__ void solve_one(const BatchArgs& args, BatchSys& S, BatchSlot& W, doub
             if (!isfinite(est)) { err = true; break; }
             if (est <= tol_abs || lucky || q < s) break;
         }
-        if (err) { status = SSTEP_ERR_NONFINITE; break; }
-        // y = R^{-1} rhs, assembly coefficients
-        if (tid == 0) scalar_ysolve(W, ncols, s, ldg, lm);
+        if (err) { status = tm.failed ? SSTEP_ERR_HIP : SSTEP_ERR_NONFINITE; break; }
+        // y = R^{-1} rhs, assembly x += V y on own rows; the residual that
+        // follows reads neighbouring members' rows of x
+        if (tid == 0) scalar_ysolve(W, ncols, s, ldg_, lm);
         __syncthreads();
-        wg_lincomb<NT, 1>(V, ld, ncols, lm, 1, S.x, N, 1, N, false);
-        __syncthreads();
+        wg_lincomb<NT, 1>(V, ld, ncols, lm, 1, S.x, N, 1, R, false);
+        team_barrier(tm);
         pc.lap(SSTEP_K_UPDATE);
     }
-    if (tid == 0) {
+    if (tid == 0 && tm.rank == 0) {
         S.status = status;
         S.blocks = blocks;
         S.cycles = cycles;
+        S.team = tm.T;
         S.rel_resid = fnorm > 0.0 ? beta / fnorm : beta;
-        for (int c = 0; c < SSTEP_K_NCLASS; ++c) S.ticks[c] = pc.acc[c];
+        for (int c = 0; c < SSTEP_K_NCLASS; ++c) S.ticks[c] = L.clk[c];
     }
     __syncthreads();
 }
@@ -571,32 +693,91 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
     __shared__ double lw[kMaxS * kMaxS];
     __shared__ GramFactor lf;
     __shared__ double lm[512 * 8];  // update / assembly coefficients
+    __shared__ double l1[2];
     __shared__ StencilView sA;      // the current system's operator
     __shared__ long long clk[SSTEP_K_NCLASS + 1];
+    __shared__ Team tm;
     __shared__ int next;
+    const WgShared L{red, sh, lw, &lf, lm, l1, clk};
     BatchSlot& W = args.slots[blockIdx.x];
+    int* abort = args.queue + 2;
+
+    // phase 1: large systems, teams of args.team workgroups on one XCD
+    if (args.team > 1 && args.nbig > 0) {
+        if (threadIdx.x == 0) {
+            const int T = args.team, G = gridDim.x, b = blockIdx.x;
+            const int per_xcd = G / 8, tpx = per_xcd / T;
+            const int x = b % 8, k = b / 8;
+            const int id = x * tpx + k / T;
+            tm.T = T;
+            tm.rank = k % T;
+            tm.parity = 0;
+            tm.failed = 0;
+            tm.target = 0;
+            tm.cnt = args.team_sync + (size_t)id * 64;
+            tm.mailbox = (int*)(args.team_sync + (size_t)id * 64 + 32);
+            tm.abort = abort;
+            tm.limit = args.spin_limit;
+            for (int r = 0; r < T; ++r) tm.member[r] = args.slots + ((k / T) * T + r) * 8 + x;
+        }
+        __syncthreads();
+        for (;;) {
+            if (tm.rank == 0 && threadIdx.x == 0) {
+                const int k = atomicAdd(args.queue + 0, 1);
+                __hip_atomic_store(tm.mailbox, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (!team_barrier(tm)) break;
+            if (threadIdx.x == 0)
+                next = __hip_atomic_load(tm.mailbox, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const int k = next;
+            if (k >= args.nbig) break;
+            BatchSys& S = args.sys[args.order_big[k]];
+            if (threadIdx.x == 0) sA = S.A;
+            __syncthreads();
+            solve_sys<NT, CA, KZ>(args, S, W, L, sA, tm);
+            if (tm.failed) break;
+        }
+        __syncthreads();
+    }
+    // phase 2: small systems, one workgroup each
+    if (threadIdx.x == 0) {
+        tm.T = 1;
+        tm.rank = 0;
+        tm.parity = 0;
+        tm.failed = 0;
+    }
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(args.queue, 1);
+        if (threadIdx.x == 0)
+            next = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       ? args.nsmall
+                       : atomicAdd(args.queue + 1, 1);
         __syncthreads();
         const int k = next;
         __syncthreads();
-        if (k >= args.nsys) break;
-        BatchSys& S = args.sys[args.order[k]];
+        if (k >= args.nsmall) break;
+        BatchSys& S = args.sys[args.order_small[k]];
         if (threadIdx.x == 0) sA = S.A;
         __syncthreads();
-        solve_one<NT, CA, KZ>(args, S, W, red, sh, lw, &lf, lm, sA, clk);
+        solve_sys<NT, CA, KZ>(args, S, W, L, sA, tm);
     }
 }
 
-// queue reset, recorded as a kernel node (no memset node in the graph)
-static __global__ void k_batch_reset(int* queue) { *queue = 0; }
+// queue words, abort flag and team counters, cleared by a kernel (recorded as
+// a kernel node in the graph: no memset node)
+static __global__ void k_batch_reset(int* queue, unsigned* team_sync, int nwords) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 4) queue[i] = 0;
+    if (i < nwords) team_sync[i] = 0u;
+}
 
 // ---------------------------------------------------------------------------
-// host side: a plan uploads the system table once, captures the queue reset
-// and the persistent launch in a hipGraph, and replays it per execution.
+// host side: a plan uploads the system table once, captures the reset and the
+// persistent launch in a hipGraph, and replays it per execution.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-    int nsys = 0, s = 0, m = 0, threads = 512, wgs_per_cu = 1, nslots = 0;
+    int nsys = 0, s = 0, m = 0, threads = 512, wgs_per_cu = 1, nslots = 0, team = 1, nteam_words = 0;
     double tick_khz = 1e5;  // wall-clock rate of the device (kHz)
     hipStream_t st = nullptr;
     void* ws = nullptr;
@@ -608,8 +789,28 @@ struct BatchPlan {
     BatchArgs args{};
 };
 
+template <int NT, int CA, int KZ>
+static const void* batch_kernel() {
+    return reinterpret_cast<const void*>(&k_batched_gmres<NT, CA, KZ>);
+}
+
+// kernel instance for (threads, s): s <= 4 uses 4-column Gram / update lanes,
+// s <= 8 eight
+static const void* batch_kernel_for(int threads, int s) {
+    if (s <= 4) {
+        if (threads == 256) return batch_kernel<256, 8, 4>();
+        if (threads == 512) return batch_kernel<512, 8, 4>();
+        return batch_kernel<1024, 4, 4>();
+    }
+    if (threads == 256) return batch_kernel<256, 4, 8>();
+    if (threads == 512) return batch_kernel<512, 4, 8>();
+    return batch_kernel<1024, 2, 8>();
+}
+
 static void batch_enqueue(const BatchPlan& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, P.args.queue);
+    const int nw = std::max(P.nteam_words, 4);
+    hipLaunchKernelGGL(k_batch_reset, dim3((nw + 255) / 256), dim3(256), 0, s, P.args.queue,
+                       P.args.team_sync, P.nteam_words);
     const dim3 g(P.nslots);
 #define SSTEP_BATCH(NT, CA, KZ) \
     hipLaunchKernelGGL((k_batched_gmres<NT, CA, KZ>), g, dim3(NT), 0, s, P.args)
@@ -625,20 +826,25 @@ static void batch_enqueue(const BatchPlan& P, hipStream_t s) {
 #undef SSTEP_BATCH
 }
 
+// slots: compute units x workgroups per CU (every workgroup resident); without
+// teams no more workgroups than systems
+int batched_slots(int nsys, int wgs_per_cu, int team) {
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int full = std::max(1, ncu) * wgs_per_cu;
+    return team > 1 ? full : std::min(nsys, full);
+}
+
 size_t batched_workspace_bytes(int nsys, const sstep_stencil* A, int s, int m, int nslots) {
     size_t tot = 0;
     for (int i = 0; i < nsys; ++i)
         tot += ((size_t)(m * s + 1) * col_stride(grid_points(A[i])) * sizeof(double) + 255) / 256 * 256;
     tot += (sizeof(BatchSlot) * (size_t)nslots + 255) / 256 * 256 + 4096 +
-           (sizeof(BatchSys) * (size_t)nsys + 255) / 256 * 256 + (sizeof(int) * (size_t)nsys + 255) / 256 * 256;
+           (sizeof(unsigned) * 64 * (size_t)nslots + 255) / 256 * 256 +
+           (sizeof(BatchSys) * (size_t)nsys + 255) / 256 * 256 +
+           2 * ((sizeof(int) * (size_t)nsys + 255) / 256 * 256);
     return tot;
-}
-
-int batched_slots(int nsys, int wgs_per_cu) {
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    return std::min(nsys, std::max(1, ncu) * wgs_per_cu);
 }
 
 int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const double* const* f,
@@ -649,7 +855,8 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
     P->m = m;
     P->threads = opt.batch_threads > 0 ? opt.batch_threads : 512;
     P->wgs_per_cu = opt.batch_wgs_per_cu > 0 ? opt.batch_wgs_per_cu : 1;
-    P->nslots = batched_slots(nsys, P->wgs_per_cu);
+    P->team = opt.batch_team > 0 ? opt.batch_team : 1;
+    P->nslots = batched_slots(nsys, P->wgs_per_cu, P->team);
     P->st = (hipStream_t)opt.stream;
     {
         int dev = 0, khz = 0;
@@ -659,6 +866,20 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
         else
             (void)hipGetLastError();
     }
+    // teams need every workgroup resident and whole teams inside each XCD
+    if (P->team > 1) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel_for(P->threads, s),
+                                                         P->threads, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            occ = 0;
+        }
+        if (occ < P->wgs_per_cu || P->nslots % (8 * P->team) != 0) {
+            P->team = 1;
+            P->nslots = batched_slots(nsys, P->wgs_per_cu, 1);
+        }
+    }
+    P->nteam_words = P->nslots * 64;
     const size_t need = batched_workspace_bytes(nsys, A, s, m, P->nslots);
     if (opt.workspace) {
         if (opt.workspace_bytes < need || ((uintptr_t)opt.workspace & 255u)) {
@@ -684,8 +905,10 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
         };
         BatchSlot* slots = (BatchSlot*)take(sizeof(BatchSlot) * P->nslots);
         int* queue = (int*)take(4096);
+        unsigned* team_sync = (unsigned*)take(sizeof(unsigned) * 64 * (size_t)P->nslots);
         P->dsys = (BatchSys*)take(sizeof(BatchSys) * nsys);
-        int* dorder = (int*)take(sizeof(int) * nsys);
+        int* dbig = (int*)take(sizeof(int) * nsys);
+        int* dsmall = (int*)take(sizeof(int) * nsys);
         P->hs.resize(nsys);
         for (int i = 0; i < nsys; ++i) {
             BatchSys& b = P->hs[i];
@@ -696,22 +919,37 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
             b.ld = col_stride(b.A.N);
             b.ws = (double*)take((size_t)(m * s + 1) * b.ld * sizeof(double));
             // sigma: power-of-two Gershgorin bound (per-point coefficients are
-            // scanned on the device; the queue word is free scratch until launch)
+            // scanned on the device; the queue words are free scratch until launch)
             b.sigma = op_params(A[i], opt.sigma, P->st, (double*)queue).sigma;
         }
         std::vector<int> order(nsys);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(),
                          [&](int a, int b) { return P->hs[a].A.N > P->hs[b].A.N; });
+        // large systems go to the teams: at least 16384 points and 4 grid rows
+        // per member
+        std::vector<int> big, small;
+        for (int i : order) {
+            const long long rows = (long long)P->hs[i].A.ny * P->hs[i].A.nz;
+            const bool is_big = P->team > 1 && P->hs[i].A.N >= (long long)P->team * 16384 &&
+                                rows >= 4LL * P->team;
+            (is_big ? big : small).push_back(i);
+        }
+        if (!big.empty())
+            SSTEP_HIP(hipMemcpyAsync(dbig, big.data(), sizeof(int) * big.size(),
+                                     hipMemcpyHostToDevice, P->st));
+        if (!small.empty())
+            SSTEP_HIP(hipMemcpyAsync(dsmall, small.data(), sizeof(int) * small.size(),
+                                     hipMemcpyHostToDevice, P->st));
         SSTEP_HIP(hipMemcpyAsync(P->dsys, P->hs.data(), sizeof(BatchSys) * nsys,
                                  hipMemcpyHostToDevice, P->st));
-        SSTEP_HIP(hipMemcpyAsync(dorder, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice,
-                                 P->st));
         SSTEP_HIP(hipStreamSynchronize(P->st));
         BatchArgs& args = P->args;
         args.sys = P->dsys;
-        args.order = dorder;
-        args.nsys = nsys;
+        args.order_big = dbig;
+        args.order_small = dsmall;
+        args.nbig = (int)big.size();
+        args.nsmall = (int)small.size();
         args.s = s;
         args.m = m;
         args.tol = tol;
@@ -720,6 +958,9 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
         args.lucky_tol = 1e-14;
         args.slots = slots;
         args.queue = queue;
+        args.team_sync = team_sync;
+        args.team = P->team;
+        args.spin_limit = 1LL << 22;  // seconds of polling per barrier before giving up
         if (opt.batch_graph) {
             // capture on a private stream (capture needs a non-default stream)
             hipStream_t cs;
@@ -767,6 +1008,7 @@ int batched_plan_execute(void* plan, sstep_info* info, double* ms_out) {
             info[i].rel_resid = b.rel_resid;
             info[i].sigma = b.sigma;
             info[i].ms_total = ms;
+            info[i].matvecs = b.team;  // workgroups that solved this system
             for (int c = 0; c < SSTEP_K_NCLASS; ++c) info[i].ms[c] = (double)b.ticks[c] / P->tick_khz;
         }
         if (b.status < 0 && status >= 0) status = b.status;

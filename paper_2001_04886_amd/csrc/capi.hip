@@ -186,6 +186,9 @@ static int batch_args_ok(int nsys, const sstep_stencil* A, const double* const* 
             opt->batch_threads != 1024)
             return 0;
         if (opt->batch_wgs_per_cu < 0 || opt->batch_wgs_per_cu > 4) return 0;
+        if (opt->batch_team != 0 && opt->batch_team != 1 && opt->batch_team != 2 &&
+            opt->batch_team != 4 && opt->batch_team != 8)
+            return 0;
     }
     for (int i = 0; i < nsys; ++i) {
         if (!stencil_ok(&A[i]) || !f[i] || !x[i]) return 0;
@@ -201,7 +204,8 @@ size_t sstep_batch_workspace_bytes(int nsys, const sstep_stencil* A, int s, int 
     for (int i = 0; i < nsys; ++i)
         if (!stencil_ok(&A[i])) return 0;
     const int wpc = (opt && opt->batch_wgs_per_cu > 0) ? opt->batch_wgs_per_cu : 1;
-    return batched_workspace_bytes(nsys, A, s, m, batched_slots(nsys, wpc));
+    const int team = (opt && opt->batch_team > 0) ? opt->batch_team : 1;
+    return batched_workspace_bytes(nsys, A, s, m, batched_slots(nsys, wpc, team));
 }
 
 int sstep_batch_plan_create(sstep_batch_plan* plan, int nsys, const sstep_stencil* A,

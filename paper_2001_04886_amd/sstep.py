@@ -46,7 +46,7 @@ class OptionsC(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("batch_threads", C.c_int32),
                 ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("batch_team", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -216,7 +216,7 @@ def _stream(stream=None) -> int:
 
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
             workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
-            batch_graph=False) -> OptionsC:
+            batch_graph=False, batch_team=0) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -232,6 +232,7 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
     o.batch_threads = int(batch_threads)
     o.batch_wgs_per_cu = int(batch_wgs_per_cu)
     o.batch_graph = 1 if batch_graph else 0
+    o.batch_team = int(batch_team)
     return o
 
 
@@ -316,7 +317,7 @@ class BatchPlan:
     solution at every execute(); reset it to the initial guess first)."""
 
     def __init__(self, stencils, fs, xs, s, m, tol, threads=0, wgs_per_cu=0, graph=True,
-                 max_iters=0, workspace=None):
+                 max_iters=0, workspace=None, team=0):
         n = len(stencils)
         if not (len(fs) == len(xs) == n):
             raise ValueError("stencils, fs and xs must have equal lengths")
@@ -326,7 +327,7 @@ class BatchPlan:
         self._x = (C.c_void_p * n)(*[_f64(x, a.N, "x") for x, a in zip(xs, stencils)])
         self._keep = (list(fs), list(xs), workspace)
         o = options(max_iters=max_iters, workspace=workspace, batch_threads=threads,
-                    batch_wgs_per_cu=wgs_per_cu, batch_graph=graph)
+                    batch_wgs_per_cu=wgs_per_cu, batch_graph=graph, batch_team=team)
         self._plan = C.c_void_p()
         _check(load().sstep_batch_plan_create(C.byref(self._plan), n, self._A, self._f, self._x,
                                               s, m, tol, C.byref(o)), "batch_plan_create")
@@ -351,13 +352,13 @@ class BatchPlan:
             pass
 
 
-def batch_workspace_bytes(stencils, s, m, wgs_per_cu=0) -> int:
+def batch_workspace_bytes(stencils, s, m, wgs_per_cu=0, team=0) -> int:
     n = len(stencils)
     arr = (StencilC * n)(*[a.c_struct() for a in stencils])
-    o = StencilC  # noqa: F841
     opt = OptionsC()
     load().sstep_default_options(C.byref(opt))
     opt.batch_wgs_per_cu = int(wgs_per_cu)
+    opt.batch_team = int(team)
     return int(load().sstep_batch_workspace_bytes(n, arr, s, m, C.byref(opt)))
 
 

@@ -1,11 +1,11 @@
 """Autotuner for the batched persistent solver's launch shape.
 
 Candidate shapes (threads per workgroup x resident workgroups per compute
-unit) are timed on the actual batch -- one warm-up and one timed execution of
-the captured graph each -- and the fastest is cached in a JSON table keyed by
-GPU architecture, batch signature (count, total unknowns, largest system), s
-and m.  The table lives next to this module (``tuned/batched.json``) unless a
-path is given.
+unit x workgroups per team on large systems) are timed on the actual batch --
+two executions of the captured graph each, the faster kept -- and the fastest
+is cached in a JSON table keyed by GPU architecture, batch signature (count,
+total unknowns, largest system), s and m.  The table lives next to this
+module (``tuned/batched.json``) unless a path is given.
 """
 from __future__ import annotations
 
@@ -15,7 +15,8 @@ import time
 
 from . import sstep as S
 
-CANDIDATES = ((256, 1), (256, 2), (512, 1), (512, 2), (1024, 1))
+CANDIDATES = ((256, 2, 1), (512, 1, 1), (512, 1, 2), (512, 1, 4), (1024, 1, 1), (1024, 1, 2),
+              (1024, 1, 4))
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "batched.json")
 
 
@@ -40,21 +41,22 @@ def load_cache(path=DEFAULT_CACHE):
 
 def lookup(stencils, s, m, path=DEFAULT_CACHE):
     rec = load_cache(path).get(batch_key(stencils, s, m))
-    return (rec["threads"], rec["wgs_per_cu"]) if rec else None
+    if not rec or "team" not in rec:
+        return None
+    return rec["threads"], rec["wgs_per_cu"], rec["team"]
 
 
 def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAULT_CACHE,
                  max_iters=0, log=None):
-    """Time every candidate shape on this batch; returns (threads, wgs_per_cu)
-    of the fastest and records all timings in the cache."""
+    """Time every candidate shape on this batch; returns (threads, wgs_per_cu,
+    team) of the fastest and records all timings in the cache."""
     import torch
-    wpc_max = max(w for _, w in candidates)
-    nb = S.batch_workspace_bytes(stencils, s, m, wpc_max)
+    nb = max(S.batch_workspace_bytes(stencils, s, m, w, t) for _, w, t in candidates)
     ws = torch.empty(nb, dtype=torch.uint8, device=xs[0].device)
     times = {}
-    for threads, wpc in candidates:
+    for threads, wpc, team in candidates:
         plan = S.BatchPlan(stencils, fs, xs, s, m, tol, threads=threads, wgs_per_cu=wpc,
-                           graph=True, max_iters=max_iters, workspace=ws)
+                           graph=True, max_iters=max_iters, workspace=ws, team=team)
         best = None
         for _ in range(2):
             for x in xs:
@@ -65,16 +67,16 @@ def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAUL
             t = time.perf_counter() - t0
             best = t if best is None else min(best, t)
         plan.close()
-        times[f"{threads}x{wpc}"] = best
+        times[f"{threads}x{wpc}x{team}"] = best
         if log:
-            log(f"# tune batched: threads={threads} wgs/CU={wpc}: {best * 1e3:.1f} ms")
+            log(f"# tune batched: threads={threads} wgs/CU={wpc} team={team}: {best * 1e3:.1f} ms")
     key = min(times, key=times.get)
-    threads, wpc = (int(v) for v in key.split("x"))
+    threads, wpc, team = (int(v) for v in key.split("x"))
     cache = load_cache(path)
-    cache[batch_key(stencils, s, m)] = {"threads": threads, "wgs_per_cu": wpc,
+    cache[batch_key(stencils, s, m)] = {"threads": threads, "wgs_per_cu": wpc, "team": team,
                                         "ms": {k: v * 1e3 for k, v in times.items()}}
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     del ws
-    return threads, wpc
+    return threads, wpc, team

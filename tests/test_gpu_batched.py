@@ -195,3 +195,52 @@ def test_batched_variable_coefficients_fixed_blocks():
             continue
         assert info.iters == res.iters == 12
         assert rel(x.cpu().numpy(), xo) <= 1e-8, (p.nx, rel(x.cpu().numpy(), xo))
+
+
+@pytest.mark.parametrize("team,threads", [(2, 1024), (4, 512), (8, 1024)])
+def test_batched_teams_match_oracle(team, threads):
+    # large systems (>= 16384 points per member) are solved by teams of
+    # workgroups, the rest one workgroup each; 2-D and 3-D, odd widths
+    big = [PB.convdiff(2, 263, 40.0, seed=1200), PB.convdiff(2, 300, 5.0, seed=1201),
+           PB.convdiff(3, 51, 50.0, seed=1202)]
+    small = [PB.convdiff(2, n, g, seed=1210 + i) for i, (n, g) in enumerate([(33, 10.0), (20, 60.0)])]
+    probs = big + small
+    fs = [O.apply(operator(p), p.x_true()) for p in probs]
+    # a fixed number of blocks: the iterates match the oracle's
+    status, infos, xs = run_batch(probs, fs, 4, 6, 0.0, max_iters=9, threads=threads, team=team)
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        xo, res = O.sgmres(operator(p), f, np.zeros(p.N), 4, 6, 0.0, max_blocks=9)
+        assert info.iters == res.iters == 9 and info.cycles == res.cycles
+        assert rel(x, xo) <= 1e-8, (p.nx, rel(x, xo))
+    # members per system: teams take systems of >= 16384 points and 4 grid rows per member
+    expect = [team if (p.N >= team * 16384 and p.ny * p.nz >= 4 * team) else 1 for p in probs]
+    assert [i.matvecs for i in infos] == expect
+    assert expect[2] == team
+    # converged: the true residual meets the tolerance
+    status, infos, xs = run_batch(probs, fs, 4, 10, 1e-8, threads=threads, team=team)
+    assert status == S.OK
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        assert info.status == S.OK
+        assert np.linalg.norm(f - O.apply(operator(p), x)) / np.linalg.norm(f) <= 1e-8
+
+
+def test_batched_teams_graph_replays_identical():
+    probs = [PB.convdiff(2, 256, 30.0, seed=1300), PB.convdiff(2, 40, 30.0, seed=1301)]
+    fs = [O.apply(operator(p), p.x_true()) for p in probs]
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fd = [torch.from_numpy(f).to(DEV) for f in fs]
+    xd = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
+    plan = S.BatchPlan(st, fd, xd, 4, 8, 1e-9, threads=1024, team=4, graph=True)
+    ref = None
+    for rep in range(3):
+        for x in xd:
+            x.zero_()
+        status, infos = plan.execute()
+        assert status == S.OK and infos[0].matvecs == 4
+        got = [x.cpu().numpy().copy() for x in xd]
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b)
+    plan.close()
