@@ -214,7 +214,9 @@ int sstep_stencil_apply(const sstep_stencil *A, const double *x, double *y, void
  * is the input w (read), columns 1..s are written:
  *   basis 0: y_0 = w * in_scale, y_j = A y_{j-1} / sigma
  *   basis 1: y_1 = (A - c) y_0 / d, y_{j+1} = 2 (A - c) y_j / d - y_{j-1}
- * Column 0 itself is not rewritten (it keeps w; y_0 is w * in_scale). */
+ * Column 0 itself is not rewritten (it keeps w; y_0 is w * in_scale).
+ * Always the fused (several levels per pass) kernel, whatever the grid size;
+ * the solvers switch to one stencil launch per level on small grids. */
 int sstep_kernel_mpk(const sstep_stencil *A, double *Y, int64_t ldy, int s, int basis,
                      double in_scale, double sigma, double cheb_c, double cheb_d,
                      void *stream);

@@ -270,7 +270,7 @@ int sstep_kernel_mpk(const sstep_stencil* A, double* Y, int64_t ldy, int s, int 
         SSTEP_HIP(hipMallocAsync((void**)&d, sizeof(double), c.st));
         SSTEP_HIP(hipMemcpyAsync(d, &in_scale, sizeof(double), hipMemcpyHostToDevice, c.st));
         OpParams P{sigma, cheb_c, cheb_d};
-        launch_mpk<double>(c, v, Y, ldy, s, basis, P, d, nullptr);
+        launch_mpk<double>(c, v, Y, ldy, s, basis, P, d, nullptr, /*fused_only=*/true);
         SSTEP_HIP(hipFreeAsync(d, c.st));
         SSTEP_HIP(hipStreamSynchronize(c.st));
         return SSTEP_OK;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/sstep.h"
+#include "gram_self.hpp"
 #include "kernels.hpp"
 #include "mpk.hpp"
 
@@ -263,12 +264,59 @@ inline void mpk_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T
                        prev_scale, lv, ntx, nty, zchunk, skip);
 }
 
+// Workgroups a fused matrix-powers launch of L levels would use (the geometry
+// of mpk_go).
+inline long long mpk_fused_wgs(const StencilView& v, int L) {
+    const bool d3 = v.ndim == 3;
+    const int PX = d3 ? 32 : 256, PY = d3 ? 32 : 1;
+    const int IX = PX - 2 * L, IY = d3 ? PY - 2 * L : 1;
+    const long long ntx = (v.nx + IX - 1) / IX, nty = d3 ? (v.ny + IY - 1) / IY : 1;
+    const int nmarch = d3 ? v.nz : v.ny;
+    const long long tiles = ntx * nty, target = d3 ? 2048 : 1024;
+    const long long nch = std::max<long long>(1, (target + tiles - 1) / tiles);
+    const long long zchunk = std::max<long long>((d3 ? 2 : 4) * L, (nmarch + nch - 1) / nch);
+    return tiles * ((nmarch + zchunk - 1) / zchunk);
+}
+
+// Level coefficients of the monomial / Chebyshev recurrence at global level
+// lev = 1..s: y_lev = alpha A y_{lev-1} + beta y_{lev-1} + gam y_{lev-2}.
+inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, double* b,
+                            double* g) {
+    if (basis == SSTEP_BASIS_CHEBYSHEV) {
+        *a = (lev == 1 ? 1.0 : 2.0) / P.cd;
+        *b = -(lev == 1 ? 1.0 : 2.0) * P.cc / P.cd;
+        *g = lev == 1 ? 0.0 : -1.0;
+    } else {
+        *a = 1.0 / P.sigma;
+        *b = 0.0;
+        *g = 0.0;
+    }
+}
+
 // Matrix powers of column 0 of Y into columns 1..s: fused launches of at
-// most kMpkMaxL levels each.  Column 0 is read with in_scale applied.
+// most kMpkMaxL levels each.  Column 0 is read with in_scale applied.  Grids
+// too small to give a fused launch 512 workgroups (a few hundred rows) run one
+// stencil launch per level instead (unless fused_only): their vectors sit in
+// L2, and a fused pass would march few workgroups through many halo rows.
 template <typename T>
 inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s, int basis,
-                       const OpParams& P, const double* in_scale, const int* skip) {
+                       const OpParams& P, const double* in_scale, const int* skip,
+                       bool fused_only = false) {
     const double vb = (double)v.N * sizeof(T);
+    const int L0 = v.ndim == 3 ? std::min(s, 2) : (s >= 8 ? 8 : (s >= 6 ? 6 : (s >= 4 ? 4 : s)));
+    if (!fused_only && mpk_fused_wgs(v, L0) < 512) {
+        for (int lev = 1; lev <= s; ++lev) {
+            double a, b, g;
+            mpk_level_coefs(lev, basis, P, &a, &b, &g);
+            const T* in = Y + (long long)(lev - 1) * ldy;
+            const T* prev = lev >= 2 ? Y + (long long)(lev - 2) * ldy : nullptr;
+            // algorithmic bytes of the whole call: read 1, write s
+            launch_level<T>(c, v, in, lev == 1 ? in_scale : nullptr, prev,
+                            lev == 2 ? in_scale : nullptr, a, b, g, Y + (long long)lev * ldy,
+                            skip, vb * (lev == 1 ? 2.0 : 1.0));
+        }
+        return;
+    }
     int j0 = 0;
     while (j0 < s) {
         const int left = s - j0;
@@ -277,18 +325,8 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
         const int L = v.ndim == 3 ? std::min(left, 2)
                                   : (left >= 8 ? 8 : (left >= 6 ? 6 : (left >= 4 ? 4 : left)));
         MpkLevels lv;
-        for (int j = 0; j < L; ++j) {
-            const int lev = j0 + j + 1;  // global level index
-            if (basis == SSTEP_BASIS_CHEBYSHEV) {
-                lv.alpha[j] = (lev == 1 ? 1.0 : 2.0) / P.cd;
-                lv.beta[j] = -(lev == 1 ? 1.0 : 2.0) * P.cc / P.cd;
-                lv.gam[j] = lev == 1 ? 0.0 : -1.0;
-            } else {
-                lv.alpha[j] = 1.0 / P.sigma;
-                lv.beta[j] = 0.0;
-                lv.gam[j] = 0.0;
-            }
-        }
+        for (int j = 0; j < L; ++j)  // global level index j0 + j + 1
+            mpk_level_coefs(j0 + j + 1, basis, P, &lv.alpha[j], &lv.beta[j], &lv.gam[j]);
         const T* in = Y + (long long)j0 * ldy;
         const double* isc = j0 == 0 ? in_scale : nullptr;
         const T* prev = j0 >= 1 ? Y + (long long)(j0 - 1) * ldy : nullptr;
@@ -377,6 +415,23 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
     // algorithmic bytes: every distinct column read once
     const int ncols = (Z1 == X && ldz1 == ldx) ? std::max(ncx, nz1) + nz2 : ncx + nz;
     c.begin(cls, (double)N * sizeof(T) * ncols);  // one record: partial + reduce
+    if (Z1 == X && ldz1 == ldx && nz2 == 0 && ncx == nz1 && ncx <= 9) {
+        // a block against itself: one pass over its columns (same chunking,
+        // so the partials fit the space sized by gram_partial_doubles)
+        const dim3 g((unsigned)nchunk), b(kThreads);
+        if (ncx <= 3)
+            hipLaunchKernelGGL((k_gram_self<T, 3>), g, b, 0, c.st, X, ldx, ncx, N, chunk, KZ, part, skip);
+        else if (ncx <= 5)
+            hipLaunchKernelGGL((k_gram_self<T, 5>), g, b, 0, c.st, X, ldx, ncx, N, chunk, KZ, part, skip);
+        else
+            hipLaunchKernelGGL((k_gram_self<T, 9>), g, b, 0, c.st, X, ldx, ncx, N, chunk, KZ, part, skip);
+        SSTEP_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gram_reduce, dim3((ncx * nz + 63) / 64), dim3(kThreads), 0, c.st, part,
+                           nchunk, ncx, KZ, nz, G, skip);
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+        return;
+    }
     if (!Z2) Z2 = Z1;
 #define SSTEP_GRAM_CASE(K)                                                                      \
     case K:                                                                                     \

@@ -111,6 +111,24 @@ def test_block_gram_matches_numpy(N, ncx, ncz):
     assert np.array_equal(G, G2)
 
 
+@pytest.mark.parametrize("N,nc", [(1, 1), (5, 2), (1000, 3), (4097, 5), (65536 + 513, 9),
+                                  (300001, 4), (1024 * 1024 + 5, 9), (2 << 20, 7), (77777, 13)])
+def test_block_self_gram_matches_numpy(N, nc):
+    # X^T X of one block (the one-pass symmetric kernel for <= 9 columns, the
+    # tiled one beyond): symmetric to the bit, within the summation bound
+    rng = np.random.default_rng(N + 7 * nc)
+    ld = (N + 63) // 64 * 64
+    X = torch.zeros((nc, ld), dtype=torch.float64, device=DEV)
+    Xh = rng.standard_normal((nc, N))
+    X[:, :N] = dev(Xh)
+    G = host(S.kernel_gram(X[:, :N], X[:, :N]))
+    ref = Xh @ Xh.T
+    nrm = np.linalg.norm(Xh, axis=1)
+    assert np.all(np.abs(G - ref) <= 1e-15 * np.sqrt(N) * 8 * np.outer(nrm, nrm) + 1e-300)
+    assert np.array_equal(G, G.T)
+    assert np.array_equal(G, host(S.kernel_gram(X[:, :N], X[:, :N])))
+
+
 @pytest.mark.parametrize("N,ncx,ncy", [(1, 1, 1), (999, 0, 3), (4097, 40, 8), (100003, 13, 16),
                                        (1 << 20, 64, 1)])
 def test_block_update_matches_numpy(N, ncx, ncy):
