@@ -59,6 +59,23 @@ def measured_traffic(kind):
     return rec[kind]["hbm_bytes_per_launch"]
 
 
+def copy_bandwidth_gbs(torch, nbytes=1 << 30, reps=10):
+    """Bytes read + written per second by a device-to-device tensor copy."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def blocks_per_cycle(total_blocks, cycles, m):
     out = []
     left = total_blocks
@@ -185,6 +202,12 @@ def main():
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE, WRITE_SIZE)",
                      "algorithmic_bytes_per_launch": classes[dom]["bytes"] / max(classes[dom]["launches"], 1)},
     }
+
+    # the machine's attainable streaming rate: a device-to-device copy of
+    # 1 GiB (read + write) timed with events, next to the nominal 8 TB/s
+    cp = copy_bandwidth_gbs(torch)
+    out["roofline"]["measured_copy_GBs"] = cp
+    out["roofline"]["frac_of_copy"] = dom_gbs / cp
 
     if not args.no_plain:
         x.zero_()
