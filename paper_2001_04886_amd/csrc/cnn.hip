@@ -80,9 +80,18 @@ __global__ __launch_bounds__(kThreads) void k_rms(long long hw, const double* __
                                                   double* __restrict__ frms) {
     __shared__ double lds[4];
     const double* fp = f + (long long)blockIdx.x * hw;
-    double s = 0.0;
-    for (long long p = threadIdx.x; p < hw; p += kThreads) s += fp[p] * fp[p];
-    double v1[1] = {s}, o[1];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    long long p = threadIdx.x;
+    for (; p + 3 * kThreads < hw; p += 4 * kThreads) {
+        const double a = fp[p], b = fp[p + kThreads], c = fp[p + 2 * kThreads],
+                     d = fp[p + 3 * kThreads];
+        s0 += a * a;
+        s1 += b * b;
+        s2 += c * c;
+        s3 += d * d;
+    }
+    for (; p < hw; p += kThreads) s0 += fp[p] * fp[p];
+    double v1[1] = {(s0 + s1) + (s2 + s3)}, o[1];
     block_sum<1>(v1, lds, o);
     if (threadIdx.x == 0) frms[blockIdx.x] = o[0] > 0.0 ? sqrt(o[0] / (double)hw) : 1.0;
 }
@@ -333,43 +342,76 @@ __global__ __launch_bounds__(kThreads) void k_dgrad_out(int B, int H, int W,
     }
 }
 
-// layer 4 weight gradient: dW4[ci][tap] = sum_p g4[p] a3[p + off(tap)][ci],
-// db4 = sum_p g4[p].  Thread (pg, ci): channel ci over points p = pg mod 8 of
-// the workgroup's chunk; the 8 point groups are summed through LDS.
+// Grid coordinates (x, y) of the points p0 + g, p0 + g + step, ... advanced
+// without divisions (the sample index is not needed: offsets stay in-sample).
+struct PixWalk {
+    int x, y, W, H;
+    long long sbase;  // first point of the current sample
+    __device__ PixWalk(long long p, int W_, int H_) : W(W_), H(H_) {
+        const long long hw = (long long)W_ * H_;
+        sbase = p - p % hw;
+        const int r = (int)(p - sbase);
+        y = r / W_;
+        x = r - y * W_;
+    }
+    __device__ __forceinline__ void advance(int step) {
+        x += step;
+        while (x >= W) {
+            x -= W;
+            if (++y == H) {
+                y = 0;
+                sbase += (long long)W * H;
+            }
+        }
+    }
+};
+
+// Thin-layer weight gradients: thread (pg, task) with task = tap * 4 + cq
+// (cq: a chunk of 8 channels, one 16-byte load), pg = 0..6 a point group
+// (points p0 + pg, p0 + pg + 7, ... of the workgroup's chunk); the point
+// groups are summed through LDS in order.
+constexpr int TG_TASKS = 36, TG_GROUPS = kThreads / TG_TASKS;  // 7 groups (252 threads)
+
+// layer 4: dW4[ci][tap] = sum_p g4[p] a3[p + off(tap)][ci], db4 = sum_p g4[p].
 __global__ __launch_bounds__(kThreads) void k_wgrad_out(int B, int H, int W, long long chunk,
                                                         const float* __restrict__ g4,
                                                         const bf16* __restrict__ a3,
                                                         float* __restrict__ part) {
-    __shared__ float red[8][PS4 + 3];
-    const int ci = threadIdx.x & 31, pg = threadIdx.x >> 5;
+    __shared__ float red[TG_GROUPS][PS4 + 3];
+    const int task = threadIdx.x % TG_TASKS, pg = threadIdx.x / TG_TASKS;
+    const int tap = task >> 2, cq = task & 3;
+    const int dy = (tap / 3 - 1) * DIL4, dx = (tap % 3 - 1) * DIL4;
     const long long npix = (long long)B * H * W;
     const long long p0 = (long long)blockIdx.x * chunk;
     const long long p1 = p0 + chunk < npix ? p0 + chunk : npix;
-    float acc[9], bacc = 0.f;
+    float acc[8], bacc = 0.f;
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) acc[tap] = 0.f;
-    for (long long p = p0 + pg; p < p1; p += 8) {
-        const int x = (int)(p % W);
-        const int y = (int)((p / W) % H);
-        const long long sbase = p - x - (long long)y * W;
-        const float g = g4[p];
-        bacc += g;
+    for (int e = 0; e < 8; ++e) acc[e] = 0.f;
+    if (pg < TG_GROUPS && p0 + pg < p1) {
+        PixWalk w(p0 + pg, W, H);
+        for (long long p = p0 + pg; p < p1; p += TG_GROUPS, w.advance(TG_GROUPS)) {
+            const float g = g4[p];
+            if (task == 0) bacc += g;
+            const int yy = w.y + dy, xx = w.x + dx;
+            if (inside(yy, xx, H, W)) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8*>(
+                    a3 + (w.sbase + (long long)yy * W + xx) * CH + cq * 8);
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int yy = y + (tap / 3 - 1) * DIL4, xx = x + (tap % 3 - 1) * DIL4;
-            if (inside(yy, xx, H, W))
-                acc[tap] += g * (float)a3[(sbase + (long long)yy * W + xx) * CH + ci];
+                for (int e = 0; e < 8; ++e) acc[e] += g * (float)v[e];
+            }
         }
     }
+    if (pg < TG_GROUPS) {
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) red[pg][ci * 9 + tap] = acc[tap];
-    if (ci == 0) red[pg][CH * 9] = bacc;
+        for (int e = 0; e < 8; ++e) red[pg][(cq * 8 + e) * 9 + tap] = acc[e];
+        if (task == 0) red[pg][CH * 9] = bacc;
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < PS4; i += kThreads) {
-        float s = 0.f;
+        float t = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s += red[q][i];
-        part[(long long)blockIdx.x * PS4 + i] = s;
+        for (int q = 0; q < TG_GROUPS; ++q) t += red[q][i];
+        part[(long long)blockIdx.x * PS4 + i] = t;
     }
 }
 
@@ -457,60 +499,88 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(int B, int H, int W, int d
     if (tid < CH) dst[CH * CH * 9 + tid] = bacc;
 }
 
-// layer 1 weight gradient: dW1[co][cin][tap] = sum_p g1[p][co] a0[p + off(tap)][cin],
-// db1[co] = sum_p g1[p][co].  Thread (pg, co) as in k_wgrad_out.
+// layer 1: dW1[co][cin][tap] = sum_p g1[p][co] a0[p + off(tap)][cin],
+// db1[co] = sum_p g1[p][co]; cq chunks the output channels co.
 __global__ __launch_bounds__(kThreads) void k_wgrad_in(int B, int H, int W, long long chunk,
                                                        const bf16* __restrict__ g1,
                                                        const bf16x2* __restrict__ a0,
                                                        float* __restrict__ part) {
-    __shared__ float red[8][PS1 + 1];
-    const int co = threadIdx.x & 31, pg = threadIdx.x >> 5;
+    __shared__ float red[TG_GROUPS][PS1 + 1];
+    const int task = threadIdx.x % TG_TASKS, pg = threadIdx.x / TG_TASKS;
+    const int tap = task >> 2, cq = task & 3;
+    const int dy = (tap / 3 - 1) * DIL1, dx = (tap % 3 - 1) * DIL1;
     const long long npix = (long long)B * H * W;
     const long long p0 = (long long)blockIdx.x * chunk;
     const long long p1 = p0 + chunk < npix ? p0 + chunk : npix;
-    float acc[9][2], bacc = 0.f;
+    float acc[8][2], bacc[8];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) acc[tap][0] = acc[tap][1] = 0.f;
-    for (long long p = p0 + pg; p < p1; p += 8) {
-        const int x = (int)(p % W);
-        const int y = (int)((p / W) % H);
-        const long long sbase = p - x - (long long)y * W;
-        const float g = (float)g1[p * CH + co];
-        bacc += g;
+    for (int e = 0; e < 8; ++e) acc[e][0] = acc[e][1] = bacc[e] = 0.f;
+    if (pg < TG_GROUPS && p0 + pg < p1) {
+        PixWalk w(p0 + pg, W, H);
+        for (long long p = p0 + pg; p < p1; p += TG_GROUPS, w.advance(TG_GROUPS)) {
+            const bf16x8 gv = *reinterpret_cast<const bf16x8*>(g1 + p * CH + cq * 8);
+            if (tap == 0) {
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int yy = y + (tap / 3 - 1) * DIL1, xx = x + (tap % 3 - 1) * DIL1;
+                for (int e = 0; e < 8; ++e) bacc[e] += (float)gv[e];
+            }
+            const int yy = w.y + dy, xx = w.x + dx;
             if (inside(yy, xx, H, W)) {
-                const bf16x2 v = a0[sbase + (long long)yy * W + xx];
-                acc[tap][0] += g * (float)v[0];
-                acc[tap][1] += g * (float)v[1];
+                const bf16x2 v = a0[w.sbase + (long long)yy * W + xx];
+                const float v0 = (float)v[0], v1 = (float)v[1];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    acc[e][0] += (float)gv[e] * v0;
+                    acc[e][1] += (float)gv[e] * v1;
+                }
             }
         }
     }
+    if (pg < TG_GROUPS) {
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        red[pg][(co * 2 + 0) * 9 + tap] = acc[tap][0];
-        red[pg][(co * 2 + 1) * 9 + tap] = acc[tap][1];
+        for (int e = 0; e < 8; ++e) {
+            const int co = cq * 8 + e;
+            red[pg][(co * 2 + 0) * 9 + tap] = acc[e][0];
+            red[pg][(co * 2 + 1) * 9 + tap] = acc[e][1];
+            if (tap == 0) red[pg][CH * 18 + co] = bacc[e];
+        }
     }
-    red[pg][CH * 18 + co] = bacc;
     __syncthreads();
     for (int i = threadIdx.x; i < PS1; i += kThreads) {
-        float s = 0.f;
+        float t = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s += red[q][i];
-        part[(long long)blockIdx.x * PS1 + i] = s;
+        for (int q = 0; q < TG_GROUPS; ++q) t += red[q][i];
+        part[(long long)blockIdx.x * PS1 + i] = t;
     }
 }
 
-// grad[i] = sum over parts (in order, FP64) of part[q][i]
+// grad[i] = sum over parts of part[q][i] (FP64): 8 outputs per workgroup; the
+// parts are cut into 32 consecutive ranges, each summed in order by one thread
+// (two interleaved accumulators), and the 32 range sums added in order.
+constexpr int RP_OUT = 8, RP_GRP = kThreads / RP_OUT;
 __global__ __launch_bounds__(kThreads) void k_reduce_parts(const float* __restrict__ part,
                                                            int npart, int psize,
                                                            float* __restrict__ grad) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= psize) return;
-    double s = 0.0;
-    for (int q = 0; q < npart; ++q) s += (double)part[(long long)q * psize + i];
-    grad[i] = (float)s;
+    __shared__ double lds[RP_GRP][RP_OUT];
+    const int lo = threadIdx.x % RP_OUT, g = threadIdx.x / RP_OUT;
+    const int i = blockIdx.x * RP_OUT + lo;
+    double s0 = 0.0, s1 = 0.0;
+    if (i < psize) {
+        const int per = (npart + RP_GRP - 1) / RP_GRP;
+        const int q0 = g * per, q1 = min(npart, q0 + per);
+        int q = q0;
+        for (; q + 1 < q1; q += 2) {
+            s0 += (double)part[(long long)q * psize + i];
+            s1 += (double)part[(long long)(q + 1) * psize + i];
+        }
+        if (q < q1) s0 += (double)part[(long long)q * psize + i];
+    }
+    lds[g][lo] = s0 + s1;
+    __syncthreads();
+    if (g == 0 && i < psize) {
+        double t = 0.0;
+        for (int r = 0; r < RP_GRP; ++r) t += lds[r][lo];
+        grad[i] = (float)t;
+    }
 }
 
 // loss = sum of partials / npix (one workgroup)
@@ -702,7 +772,7 @@ void backward(hipStream_t st, int B, int H, int W, const float* prm, const Bufs&
                        (const float*)b.t, b.g4, b.lpart);
     hipLaunchKernelGGL(k_reduce_loss, dim3(1), dim3(kThreads), 0, st, (const double*)b.lpart, lg,
                        1.0 / (double)npix, loss_dev);
-    const unsigned rb = (unsigned)((PS32 + kThreads - 1) / kThreads);
+    const unsigned rb = (unsigned)((PS32 + RP_OUT - 1) / RP_OUT);
     // layer 4
     const long long tg = thin_grid(npix), chunk = (npix + tg - 1) / tg;
     hipLaunchKernelGGL(k_wgrad_out, dim3((unsigned)tg), dim3(kThreads), 0, st, B, H, W, chunk,
