@@ -51,8 +51,7 @@ constexpr int NPARAM = OB4 + 1;
 static_assert(NPARAM == 19393, "parameter count");
 constexpr int DIL1 = 1, DIL2 = 2, DIL3 = 4, DIL4 = 8;
 
-constexpr int kGroupsPerWave = 16;  // target point groups per wave (weights amortised)
-constexpr int kMaxConvWG = 2048;
+constexpr int kMaxConvWG = 512;  // persistent conv grid: about two workgroups per CU
 constexpr int kMaxWgradWG = 1024;
 constexpr int kMaxThinWG = 2048;
 
@@ -166,29 +165,37 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(int B, int H, int W,
 //   (off(8 - tap) = -off(tap), so the adjoint is the same gather with the
 //   weights transposed and the taps reversed).
 // One wave computes 16 consecutive points of a row x 32 output channels per
-// step as two 16x16 MFMA tiles over 9 taps x 32 input channels.
+// step as two 16x16 MFMA tiles over 9 taps x 32 input channels.  The grid is
+// persistent (about two workgroups per CU): a workgroup stages the layer's
+// weights once, as bf16 in the MFMA lane order, through LDS; each wave then
+// streams point groups, the next group's nine gathers in flight while the
+// current group's 18 MFMAs run.
 template <bool DGRAD>
 __global__ __launch_bounds__(kThreads) void k_conv32(int B, int H, int W, int d,
                                                      const bf16* __restrict__ X,
                                                      const float* __restrict__ prm, int ow, int ob,
                                                      const bf16* __restrict__ mask,
                                                      bf16* __restrict__ Y) {
+    __shared__ __attribute__((aligned(16))) bf16 wl[9 * 2 * 64 * 8];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m16 = lane & 15, kq = lane >> 4;
     // A operands: row m16 (+16 h) of the output channels, k = kq*8 + e of the
-    // input channels, one per tap and half
+    // input channels, one per tap and half; entry ((tap*2 + h)*64 + lane)*8 + e
+    for (int q = threadIdx.x; q < 9 * 2 * 64 * 8; q += kThreads) {
+        const int e = q & 7, l = (q >> 3) & 63, th = q >> 9;
+        const int tap = th >> 1, h = th & 1;
+        const int mo = h * 16 + (l & 15), ki = (l >> 4) * 8 + e;
+        const float v = DGRAD ? prm[ow + (ki * CH + mo) * 9 + (8 - tap)]
+                              : prm[ow + (mo * CH + ki) * 9 + tap];
+        wl[q] = (bf16)v;
+    }
+    __syncthreads();
     bf16x8 wa[9][2];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int mo = h * 16 + m16, ki = kq * 8 + e;
-                const float v = DGRAD ? prm[ow + (ki * CH + mo) * 9 + (8 - tap)]
-                                      : prm[ow + (mo * CH + ki) * 9 + tap];
-                wa[tap][h][e] = (bf16)v;
-            }
+            wa[tap][h] = *reinterpret_cast<const bf16x8*>(wl + ((tap * 2 + h) * 64 + lane) * 8);
     float bias[2][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -198,31 +205,44 @@ __global__ __launch_bounds__(kThreads) void k_conv32(int B, int H, int W, int d,
     const int gpr = (W + 15) / 16;
     const long long ngroups = (long long)B * H * gpr;
     const long long nwaves = (long long)gridDim.x * 4;
-    for (long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * 4 + wv; g < ngroups;
-         g += nwaves) {
-        const int gx = (int)(g % gpr);
-        const long long row = g / gpr;  // b * H + y
+    // the nine 16-byte gathers of group gg (zero outside the grid)
+    auto gather = [&](long long gg, bf16x8(&dst)[9]) {
+        const int gx = (int)(gg % gpr);
+        const long long row = gg / gpr;  // b * H + y
         const int y = (int)(row % H);
-        const long long sbase = (row - y) * W;  // first point of the sample
+        const long long sbase = (row - y) * W;
         const int px = gx * 16 + m16;
-        bf16x8 bv[9];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int yy = y + (tap / 3 - 1) * d, xx = px + (tap % 3 - 1) * d;
             if (inside(yy, xx, H, W)) {
-                bv[tap] = *reinterpret_cast<const bf16x8*>(
+                dst[tap] = *reinterpret_cast<const bf16x8*>(
                     X + (sbase + (long long)yy * W + xx) * CH + kq * 8);
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bv[tap][e] = (bf16)0.f;
+                for (int e = 0; e < 8; ++e) dst[tap][e] = (bf16)0.f;
             }
         }
+    };
+    long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+    bf16x8 bn[9];
+    if (g < ngroups) gather(g, bn);
+    for (; g < ngroups; g += nwaves) {
+        bf16x8 bv[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) bv[tap] = bn[tap];
+        if (g + nwaves < ngroups) gather(g + nwaves, bn);
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tap][0], bv[tap], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tap][1], bv[tap], acc1, 0, 0, 0);
         }
+        const int gx = (int)(g % gpr);
+        const long long row = g / gpr;
+        const int y = (int)(row % H);
+        const long long sbase = (row - y) * W;
+        const int px = gx * 16 + m16;
         if (px < W) {
             const long long o = (sbase + (long long)y * W + px) * CH;
             bf16x4 r0, r1;
@@ -640,8 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_fallback_apply(long long n, const 
 inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
 inline long long conv_grid(long long groups) {
-    long long wg = (groups + 4LL * kGroupsPerWave - 1) / (4LL * kGroupsPerWave);
-    if (wg < 256) wg = (groups + 3) / 4 < 256 ? (groups + 3) / 4 : 256;
+    const long long wg = (groups + 3) / 4;
     return wg > kMaxConvWG ? kMaxConvWG : (wg < 1 ? 1 : wg);
 }
 inline long long wgrad_grid(long long units) { return units > kMaxWgradWG ? kMaxWgradWG : units; }
