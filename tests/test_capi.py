@@ -72,3 +72,74 @@ def test_solvers_reject_bad_arguments_without_launching():
     assert lib.sstep_gmres_solve(C.byref(Bad), fake, fake, 4, 4, 1e-8, None, None) == -1
     assert lib.sstep_stencil_apply(C.byref(A), fake, fake, None) == -1   # x == y
     assert lib.sstep_kernel_gram(fake, 10, 3, fake, 10, 17, 10, fake, None) == -1
+
+
+def test_network_entry_points_validate_without_launching():
+    lib = S.load()
+    assert lib.sstep_cnn_param_count() == 19393
+    # workspace: training needs the gradient buffers, inference the fallback test
+    assert lib.sstep_cnn_workspace_bytes(0, 8, 8, 1) == 0
+    tr = lib.sstep_cnn_workspace_bytes(4, 64, 48, 1)
+    inf = lib.sstep_cnn_workspace_bytes(4, 64, 48, 0)
+    assert tr > inf > 4 * 64 * 48 * (4 + 3 * 64)
+    o = S.OptionsC()
+    lib.sstep_default_options(C.byref(o))
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.sstep_cnn_forward(fake, 1.0, 0, 8, 8, fake, fake, None, fake, C.byref(o)) == S.ERR_ARG
+    assert lib.sstep_cnn_forward(fake, 0.0, 1, 8, 8, fake, fake, None, fake, C.byref(o)) == S.ERR_ARG
+    assert lib.sstep_cnn_forward(fake, 1.0, 1, 8, 8, fake, fake, None, None, C.byref(o)) == S.ERR_ARG
+    assert lib.sstep_cnn_adam(fake, fake, fake, fake, 0, 1e-3, C.byref(o)) == S.ERR_ARG
+    assert lib.sstep_cnn_train_step(fake, fake, fake, 1, -1.0, 1.0, 1, 8, 8, fake, fake, fake,
+                                    None, C.byref(o)) == S.ERR_ARG
+    A = S.Stencil(3, 8, 8, 8, (6.0, -1, -1, -1, -1, -1, -1)).c_struct()  # x0 guess is 2-D only
+    used = C.c_int(7)
+    assert lib.sstep_x0_predict(fake, 1.0, C.byref(A), fake, fake, fake, 1, C.byref(used),
+                                C.byref(o)) == S.ERR_ARG
+    assert used.value == 0
+
+
+def test_batch_options_validated_without_launching():
+    lib = S.load()
+    A = (S.StencilC * 2)(*[S.Stencil(2, 10, 10, 1, (4.0, -1, -1, -1, -1, 0, 0)).c_struct()] * 2)
+    f = (C.c_void_p * 2)(0x1000, 0x2000)
+    x = (C.c_void_p * 2)(0x3000, 0x4000)
+    plan = C.c_void_p()
+    for field, bad in (("batch_team", 3), ("batch_threads", 300), ("batch_wgs_per_cu", 5)):
+        o = S.OptionsC()
+        lib.sstep_default_options(C.byref(o))
+        setattr(o, field, bad)
+        assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, f, x, 4, 8, 1e-8, C.byref(o)) == S.ERR_ARG
+    o = S.OptionsC()
+    lib.sstep_default_options(C.byref(o))
+    assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, f, x, 9, 8, 1e-8, C.byref(o)) == S.ERR_ARG
+    misaligned = (C.c_void_p * 2)(0x1008, 0x2000)
+    assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, misaligned, x, 4, 8, 1e-8,
+                                       C.byref(o)) == S.ERR_ARG
+
+
+def test_tuner_table_lookup(tmp_path, monkeypatch):
+    import json
+    from paper_2001_04886_amd import tune as TU
+    monkeypatch.setattr(TU, "_arch", lambda: "gfx950")
+    st = [S.Stencil(2, 32, 32), S.Stencil(2, 40, 40)]
+    path = str(tmp_path / "t.json")
+    assert TU.lookup(st, 4, 30, path) is None
+    key = TU.batch_key(st, 4, 30)
+    assert key == "gfx950|n2|N2624|max1600|s4|m30"
+    json.dump({key: {"threads": 512, "wgs_per_cu": 1, "team": 2}}, open(path, "w"))
+    assert TU.lookup(st, 4, 30, path) == (512, 1, 2)
+    assert TU.lookup(st, 8, 30, path) is None
+    # a record without the team size (older table layout) is not used
+    json.dump({key: {"threads": 512, "wgs_per_cu": 1}}, open(path, "w"))
+    assert TU.lookup(st, 4, 30, path) is None
+
+
+def test_learned_model_parameters_layout():
+    from paper_2001_04886_amd import learn as LN
+    p = LN.init_params(3)
+    assert p.dtype.name == "float32" and p.size == 19393
+    # biases start at zero: b1 (32 after 576 weights), b2, b3 (32 each), b4 (1)
+    for off, n in ((576, 32), (608 + 9216, 32), (9856 + 9216, 32), (19392, 1)):
+        assert not p[off:off + n].any()
+    params, out_scale, meta = LN.load_model()
+    assert params.size == 19393 and out_scale > 0 and meta["samples"] > 0
