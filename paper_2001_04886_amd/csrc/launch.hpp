@@ -3,6 +3,8 @@
 // carving shared by the solver drivers.
 #pragma once
 
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -245,37 +247,91 @@ inline void launch_level(Ctx& c, const StencilView& v, const T* in, const double
     c.end();
 }
 
-template <typename T, int DIM, int L, int POS = (DIM == 3 ? 4 : 1)>
+// Compute units of the current device (cached per device).
+inline int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+        n = 256;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
+// Fused matrix-powers geometry: plane tiles (exact interiors of 32 x 32
+// points in 3-D, 256-point row segments in 2-D) times chunks of the march
+// axis; each chunk also computes L planes on either side.  3-D: the chunk
+// count minimises (rounds of workgroups per compute unit) x (planes marched
+// per workgroup), the time of the most loaded compute unit -- on a 256^3 grid
+// that is one 64-plane chunk per compute unit.  2-D (short workgroups that
+// need company on a compute unit to cover memory latency): about 1024
+// workgroups.
+struct MpkGeom {
+    int ntx, nty, zchunk, nzc;
+    long long wgs() const { return (long long)ntx * nty * nzc; }
+};
+inline MpkGeom mpk_geometry(const StencilView& v, int L) {
+    const bool d3 = v.ndim == 3;
+    const int IX = d3 ? 32 : 256, IY = d3 ? 32 : 1;
+    MpkGeom g;
+    g.ntx = (v.nx + IX - 1) / IX;
+    g.nty = d3 ? (v.ny + IY - 1) / IY : 1;
+    const int nmarch = d3 ? v.nz : v.ny;
+    const long long tiles = (long long)g.ntx * g.nty;
+    const int minchunk = (d3 ? 2 : 4) * L;
+    if (d3) {
+        const long long ncu = device_cus();
+        long long best = -1;
+        g.zchunk = nmarch;
+        for (int n = 1; n <= std::max(1, nmarch / minchunk); ++n) {
+            const int zc = (nmarch + n - 1) / n;
+            const long long nz = (nmarch + zc - 1) / zc;
+            const long long cost = ((tiles * nz + ncu - 1) / ncu) * (zc + 2 * L);
+            if (best < 0 || cost < best) {
+                best = cost;
+                g.zchunk = zc;
+            }
+        }
+    } else {
+        const long long nch = std::max<long long>(1, (1024 + tiles - 1) / tiles);
+        g.zchunk = (int)std::max<long long>(minchunk, (nmarch + nch - 1) / nch);
+    }
+    g.nzc = (nmarch + g.zchunk - 1) / g.zchunk;
+    return g;
+}
+
+// Grids too small for a fused pass: even with the shortest chunks it would
+// have fewer than 512 workgroups (a few hundred rows; their vectors sit in L2).
+inline bool mpk_small_grid(const StencilView& v, int L) {
+    const bool d3 = v.ndim == 3;
+    const int IX = d3 ? 32 : 256, IY = d3 ? 32 : 1;
+    const long long tiles = (long long)((v.nx + IX - 1) / IX) * (d3 ? (v.ny + IY - 1) / IY : 1);
+    const int nmarch = d3 ? v.nz : v.ny, minchunk = (d3 ? 2 : 4) * L;
+    return tiles * ((nmarch + minchunk - 1) / minchunk) < 512;
+}
+
+// The fused kernel addresses one plane of a vector (and of a coefficient
+// field, FP64) with 32-bit byte offsets.
+inline bool mpk_fused_fits(const StencilView& v) {
+    const long long plane = v.ndim == 3 ? (long long)v.nx * v.ny : v.nx;
+    return plane * 8 < (1LL << 31);
+}
+
+template <typename T, int DIM, int L>
 inline void mpk_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
                    const double* in_scale, const T* prev, const double* prev_scale,
                    const MpkLevels& lv, const int* skip) {
-    constexpr int PX = MpkTile<DIM, POS>::PX, PY = MpkTile<DIM, POS>::PY;
-    constexpr int IX = PX - 2 * L, IY = (DIM == 3) ? PY - 2 * L : 1;
-    const int ntx = (v.nx + IX - 1) / IX;
-    const int nty = (DIM == 3) ? (v.ny + IY - 1) / IY : 1;
-    const int nmarch = (DIM == 3) ? v.nz : v.ny;
-    const long long tiles = (long long)ntx * nty;
-    const long long target = (DIM == 3) ? 2048 : 1024;
-    const long long nch = std::max<long long>(1, (target + tiles - 1) / tiles);
-    const int zchunk = (int)std::max<long long>((DIM == 3 ? 2 : 4) * L, (nmarch + nch - 1) / nch);
-    const int nzc = (nmarch + zchunk - 1) / zchunk;
-    hipLaunchKernelGGL((k_mpk_fused<T, DIM, L, POS>), dim3((unsigned)(tiles * nzc)),
-                       dim3(MpkTile<DIM, POS>::THREADS), 0, c.st, v, out0, ldo, in, in_scale, prev,
-                       prev_scale, lv, ntx, nty, zchunk, skip);
-}
-
-// Workgroups a fused matrix-powers launch of L levels would use (the geometry
-// of mpk_go).
-inline long long mpk_fused_wgs(const StencilView& v, int L) {
-    const bool d3 = v.ndim == 3;
-    const int PX = d3 ? 32 : 256, PY = d3 ? 32 : 1;
-    const int IX = PX - 2 * L, IY = d3 ? PY - 2 * L : 1;
-    const long long ntx = (v.nx + IX - 1) / IX, nty = d3 ? (v.ny + IY - 1) / IY : 1;
-    const int nmarch = d3 ? v.nz : v.ny;
-    const long long tiles = ntx * nty, target = d3 ? 2048 : 1024;
-    const long long nch = std::max<long long>(1, (target + tiles - 1) / tiles);
-    const long long zchunk = std::max<long long>((d3 ? 2 : 4) * L, (nmarch + nch - 1) / nch);
-    return tiles * ((nmarch + zchunk - 1) / zchunk);
+    const MpkGeom g = mpk_geometry(v, L);
+    const dim3 grid((unsigned)g.wgs()), block(MpkTile<DIM, L>::THREADS);
+    if (v.coef)
+        hipLaunchKernelGGL((k_mpk_fused<T, DIM, L, true>), grid, block, 0, c.st, v, out0, ldo, in,
+                           in_scale, prev, prev_scale, lv, g.ntx, g.nty, g.zchunk, skip);
+    else
+        hipLaunchKernelGGL((k_mpk_fused<T, DIM, L, false>), grid, block, 0, c.st, v, out0, ldo, in,
+                           in_scale, prev, prev_scale, lv, g.ntx, g.nty, g.zchunk, skip);
 }
 
 // Level coefficients of the monomial / Chebyshev recurrence at global level
@@ -298,13 +354,14 @@ inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, do
 // too small to give a fused launch 512 workgroups (a few hundred rows) run one
 // stencil launch per level instead (unless fused_only): their vectors sit in
 // L2, and a fused pass would march few workgroups through many halo rows.
+// So do planes of 2^28 points or more, which the fused kernel cannot address.
 template <typename T>
 inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s, int basis,
                        const OpParams& P, const double* in_scale, const int* skip,
                        bool fused_only = false) {
     const double vb = (double)v.N * sizeof(T);
     const int L0 = v.ndim == 3 ? std::min(s, 2) : (s >= 8 ? 8 : (s >= 6 ? 6 : (s >= 4 ? 4 : s)));
-    if (!fused_only && mpk_fused_wgs(v, L0) < 512) {
+    if ((!fused_only && mpk_small_grid(v, L0)) || !mpk_fused_fits(v)) {
         for (int lev = 1; lev <= s; ++lev) {
             double a, b, g;
             mpk_level_coefs(lev, basis, P, &a, &b, &g);
@@ -336,8 +393,8 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
         c.begin(SSTEP_K_MPK, vb * (L + (j0 == 0 ? 1.0 : 0.0)));
 #define SSTEP_MPK(D, LL) mpk_go<T, D, LL>(c, v, out0, ldy, in, isc, prev, psc, lv, skip)
         if (v.ndim == 3) {
-            if (L == 2) mpk_go<T, 3, 2, 2>(c, v, out0, ldy, in, isc, prev, psc, lv, skip);
-            else mpk_go<T, 3, 1, 1>(c, v, out0, ldy, in, isc, prev, psc, lv, skip);
+            if (L == 2) SSTEP_MPK(3, 2);
+            else SSTEP_MPK(3, 1);
         } else {
             switch (L) {
                 case 8: SSTEP_MPK(2, 8); break;
