@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-blocks", type=int, default=2)
     ap.add_argument("--workload", choices=["gmres3d", "mixed3d", "omin2d", "small2d", "batched",
-                                           "learned"],
+                                           "learned", "paper2d"],
                     default="gmres3d")
     ap.add_argument("--nsys", type=int, default=512)
     ap.add_argument("--retune", action="store_true")
@@ -393,6 +393,74 @@ def bench_small2d(args):
           "s-GMRES(m=20, s=4) and s-Omin(k=4, s=4), FP64, tol 1e-8 (latency bound)", {"results": out})
 
 
+def bench_paper2d(args):
+    """The paper's own problem (Sec. 5, eq. (9), variable coefficients,
+    beta = 1, gamma = 50, x0 = 0.05 mod(i, 50)) on n x n grids, n in {64, 128,
+    192, 256}, stopped at the paper's rule ||r||_2 < 1e-6, with the four
+    settings of its Table 6.1 (Orthomin(4), 2-Orthomin(2), GMRES(10),
+    2-GMRES(5)), unpreconditioned.  Iterations of the HIP path and of the
+    oracle side by side (unless --no-cpu), and the solve times."""
+    import numpy as np
+    import torch
+    from paper_2001_04886_amd import problems as PB
+    from paper_2001_04886_amd import sstep as S
+    dev = torch.device("cuda:0")
+    settings = [("omin", 1, 4), ("omin", 2, 2), ("gmres", 1, 10), ("gmres", 2, 5)]
+    rows, cpu = [], None
+    for n in (64, 128, 192, 256):
+        prob = PB.paper_problem(n)
+        coef = torch.from_numpy(prob.coef).to(dev)
+        A = S.Stencil.from_problem(prob, coef)
+        g, x0 = PB.paper_rhs(n), PB.paper_x0(prob.N)
+        tol = 1e-6 / float(np.linalg.norm(g))
+        gd, x0d = torch.from_numpy(g).to(dev), torch.from_numpy(x0).to(dev)
+        x = torch.empty_like(x0d)
+        for method, s, km in settings:
+            fn = S.gmres_solve if method == "gmres" else S.omin_solve
+            mth = S.METHOD_GMRES if method == "gmres" else S.METHOD_OMIN
+            ws = S.allocate_workspace(A, mth, s, km)
+            ts = []
+            for rep in range(args.warmup + max(args.steps, 3)):
+                x.copy_(x0d)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = fn(A, gd, x, s, km, tol, max_iters=20000, workspace=ws)
+                torch.cuda.synchronize()
+                if rep >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+            xh = x.cpu().numpy()
+            row = {"n": n, "method": method, "s": s, "k_or_m": km, "iters": info.iters,
+                   "matvecs": info.matvecs, "status": info.status,
+                   "resid_2norm": info.rel_resid * float(np.linalg.norm(g)),
+                   "max_err_vs_analytic": float(np.max(np.abs(xh - PB.paper_exact(n)))),
+                   "gpu_s": sorted(ts)[len(ts) // 2]}
+            if not args.no_cpu:
+                import oracle as O
+                Ao = O.Operator(2, n, n, coef=prob.coef)
+                t0 = time.perf_counter()
+                if method == "gmres":
+                    _, res = O.sgmres(Ao, g, x0, s, km, tol, max_blocks=20000)
+                else:
+                    _, res = O.somin(Ao, g, x0, s, km, tol, max_iters=20000)
+                row["oracle_iters"], row["oracle_s"] = res.iters, time.perf_counter() - t0
+                if n == 256 and (method, s) == ("gmres", 2):
+                    cpu = {"value": row["oracle_s"], "unit": "s", "cores": 1, "kind": "oracle",
+                           "sample": "the whole 256^2 2-GMRES(5) solve, one host thread"}
+            rows.append(row)
+            print(f"# paper n={n} {method} s={s} k/m={km}: iters {info.iters}"
+                  + (f" (oracle {row['oracle_iters']})" if "oracle_iters" in row else "")
+                  + f" gpu {row['gpu_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    head = next(r for r in rows if r["n"] == 256 and r["method"] == "gmres" and r["s"] == 2)
+    extra = {"results": rows}
+    if cpu:
+        extra["cpu_baseline"] = cpu
+    _line("2-step GMRES(5) time to ||r|| < 1e-6, paper eq. (9) 256^2", head["gpu_s"], "s", False,
+          head["gpu_s"] * 1e3, args, "f64",
+          "paper eq. (9) 2-D variable-coefficient convection-diffusion, beta=1 gamma=50, "
+          "n in {64,128,192,256}, Table 6.1 settings unpreconditioned, x0 = 0.05 mod(i,50)",
+          extra)
+
+
 def bench_batched(args):
     """512 independent 2-D 5-pt systems (side ~ U{32..512}, gamma ~ U(0,100)),
     s = 4, m = 30 blocks, FP64, tol 1e-8, one persistent launch replayed from
@@ -566,6 +634,7 @@ def bench_learned(args):
 
 
 OTHER = {"mixed3d": bench_mixed3d, "omin2d": bench_omin2d, "small2d": bench_small2d,
+         "paper2d": bench_paper2d,
          "batched": bench_batched, "learned": bench_learned}
 
 

@@ -15,6 +15,8 @@ Problems
   first derivatives) with constant coefficients.
 * Variable-coefficient diffusion ``-div(k grad u) = f`` (harmonic-mean face
   coefficients) for the learned-initial-guess problem.
+* The paper's own test problem (Sec. 5, eq. (9)): variable coefficients in
+  conservative form, analytic solution, the paper's initial guess.
 * Exact solutions ``x_true[p] = 2 U(seed, p) - 1`` with ``U`` the top 53 bits of
   SplitMix64 applied to the counter ``seed * 2**40 + p`` (a counter-based
   generator, so any slice can be produced independently on any device).
@@ -118,6 +120,110 @@ def batched_table(nsys: int = 512, master_seed: int = 0, nmin: int = 32, nmax: i
     ns = nmin + np.minimum((u[:nsys] * (nmax - nmin + 1)).astype(np.int64), nmax - nmin)
     gammas = u[nsys:] * gmax
     return [(int(ns[i]), float(gammas[i]), int(master_seed * 100003 + i + 1)) for i in range(nsys)]
+
+
+# The paper's test problem (Sec. 5, eq. (9)) ----------------------------------
+#
+#   -(b u_x)_x - (c u_y)_y + (d u)_x + (e u)_y + f u = g  on (0,1)^2, u = 0 on
+#   the boundary, b = exp(-xy), c = exp(xy), d = beta (x+y), e = gamma (x+y),
+#   f = 1/(1+xy), beta = 1, gamma = 50, with g built from the analytic solution
+#   u = x exp(xy) sin(pi x) sin(pi y) (the printed test function repeats
+#   sin(pi y); the first factor is read as sin(pi x), which vanishes on the
+#   whole boundary as the Dirichlet condition needs).
+
+PAPER_BETA, PAPER_GAMMA = 1.0, 50.0
+
+
+def _grid2(n: int):
+    """Interior points of the unit square, h = 1/(n+1): arrays X, Y of shape
+    [n][n] indexed [j][i] (x fastest when flattened, point p = i + n j)."""
+    h = 1.0 / (n + 1)
+    t = (np.arange(n) + 1.0) * h
+    X, Y = np.meshgrid(t, t)
+    return X, Y, h
+
+
+def conservative_coef(n: int, b, c, d, e, f) -> np.ndarray:
+    """Per-point [7][N] stencil (centre, -x, +x, -y, +y; 0, 0) on the n x n
+    interior grid of -(b u_x)_x - (c u_y)_y + (d u)_x + (e u)_y + f u: the
+    diffusion terms as five-point conservative differences with b, c at the
+    cell faces (x +- h/2, y +- h/2), the first-order terms as central
+    differences of the products d u, e u (d, e at the neighbouring points), f at
+    the point.  b..f are functions of (x, y) arrays.  Entries of neighbours
+    outside the grid are 0 (Dirichlet 0)."""
+    X, Y, h = _grid2(n)
+
+    def ev(fn, x, y):
+        return np.broadcast_to(np.asarray(fn(x, y), dtype=np.float64), x.shape)
+
+    h2 = h * h
+    bw, be = ev(b, X - h / 2, Y), ev(b, X + h / 2, Y)
+    cs, cn = ev(c, X, Y - h / 2), ev(c, X, Y + h / 2)
+    west = -bw / h2 - ev(d, X - h, Y) / (2 * h)
+    east = -be / h2 + ev(d, X + h, Y) / (2 * h)
+    south = -cs / h2 - ev(e, X, Y - h) / (2 * h)
+    north = -cn / h2 + ev(e, X, Y + h) / (2 * h)
+    west[:, 0] = 0.0
+    east[:, -1] = 0.0
+    south[0, :] = 0.0
+    north[-1, :] = 0.0
+    coef = np.zeros((7, n * n))
+    coef[0] = ((bw + be + cs + cn) / h2 + ev(f, X, Y)).ravel()
+    coef[1], coef[2], coef[3], coef[4] = west.ravel(), east.ravel(), south.ravel(), north.ravel()
+    return coef
+
+
+def paper_functions(beta: float = PAPER_BETA, gamma: float = PAPER_GAMMA):
+    """Coefficient functions (b, c, d, e, f) of eq. (9)."""
+    return (lambda x, y: np.exp(-x * y), lambda x, y: np.exp(x * y),
+            lambda x, y: beta * (x + y), lambda x, y: gamma * (x + y),
+            lambda x, y: 1.0 / (1.0 + x * y))
+
+
+def paper_exact(n: int) -> np.ndarray:
+    """u = x exp(xy) sin(pi x) sin(pi y) at the interior grid points."""
+    X, Y, _ = _grid2(n)
+    return (X * np.exp(X * Y) * np.sin(np.pi * X) * np.sin(np.pi * Y)).ravel()
+
+
+def paper_rhs(n: int, beta: float = PAPER_BETA, gamma: float = PAPER_GAMMA) -> np.ndarray:
+    """g = L u of eq. (9) for the analytic u, at the interior grid points.
+    With E = exp(xy), sx = sin(pi x), cx = cos(pi x) (sy, cy alike):
+      u    = x E sx sy
+      u_x  = E sy ((1 + xy) sx + pi x cx)
+      u_xx = E sy ((y (2 + xy) - pi^2 x) sx + 2 pi (1 + xy) cx)
+      u_y  = x E sx (x sy + pi cy)
+      u_yy = x E sx ((x^2 - pi^2) sy + 2 pi x cy)
+    and L u = -(b_x u_x + b u_xx) - (c_y u_y + c u_yy) + d_x u + d u_x
+              + e_y u + e u_y + f u, with b_x = -y exp(-xy), c_y = x exp(xy),
+    d_x = beta, e_y = gamma."""
+    X, Y, _ = _grid2(n)
+    pi = np.pi
+    E = np.exp(X * Y)
+    sx, cx, sy, cy = np.sin(pi * X), np.cos(pi * X), np.sin(pi * Y), np.cos(pi * Y)
+    u = X * E * sx * sy
+    ux = E * sy * ((1 + X * Y) * sx + pi * X * cx)
+    uxx = E * sy * ((Y * (2 + X * Y) - pi**2 * X) * sx + 2 * pi * (1 + X * Y) * cx)
+    uy = X * E * sx * (X * sy + pi * cy)
+    uyy = X * E * sx * ((X**2 - pi**2) * sy + 2 * pi * X * cy)
+    b, c = np.exp(-X * Y), E
+    bx, cy_ = -Y * np.exp(-X * Y), X * E
+    d, e = beta * (X + Y), gamma * (X + Y)
+    f = 1.0 / (1.0 + X * Y)
+    g = -(bx * ux + b * uxx) - (cy_ * uy + c * uyy) + beta * u + d * ux + gamma * u + e * uy + f * u
+    return g.ravel()
+
+
+def paper_x0(N: int) -> np.ndarray:
+    """The paper's initial guess 0.05 * mod(i, 50) over the unknowns numbered
+    from 1 (point p = 0, 1, ... holds 0.05 * ((p + 1) mod 50))."""
+    return 0.05 * ((np.arange(N, dtype=np.int64) + 1) % 50)
+
+
+def paper_problem(n: int, beta: float = PAPER_BETA, gamma: float = PAPER_GAMMA) -> Problem:
+    """Eq. (9) on an n x n interior grid (variable coefficients [7][N])."""
+    return Problem(2, n, n, coef=conservative_coef(n, *paper_functions(beta, gamma)),
+                   name=f"paper_eq9_{n}_b{beta:g}_g{gamma:g}")
 
 
 # Gaussian random fields ----------------------------------------------------
