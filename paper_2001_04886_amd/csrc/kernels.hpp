@@ -178,102 +178,132 @@ __device__ __forceinline__ void store_pts(T* __restrict__ p, const T (&v)[PPT]) 
 }
 
 // ---------------------------------------------------------------------------
-// Block Gram, stage 1: for a point chunk and a tile of CA columns of X,
+// Block Gram, stage 1: for a point chunk and a group of 4*CAW columns of X,
 //   partial[chunk][c][j] = sum_{p in chunk} X[c][p] * Z[j][p],  j < KZ
 // Z = [Z1 (nz1 columns) | Z2 (nz2 columns)], nz1 + nz2 <= KZ.  Accumulation
-// in FP64.  The workgroups of one chunk are consecutive on one XCD, so Z is
-// read from HBM once and then served by that XCD's L2; X is streamed with
-// non-temporal loads.  The loop is software-pipelined: the loads of the next
-// step are in flight while the FMAs of the current step run.
+// in FP64.  The four waves of a workgroup walk the same points, each with
+// its own CAW columns of X (streamed with non-temporal 16-byte loads); the Z
+// tile of a step (KZ columns x 64 lanes x 16 bytes) is loaded once per
+// workgroup, two steps ahead, and read by all four waves from LDS, so Z costs
+// one L2 read per 4*CAW columns of X and few registers.  The next step's X and
+// the Z tile two steps ahead are in flight while the FMAs of the current step
+// run.  Every load in the loop is issued unconditionally (addresses past the
+// chunk clamp to its last step), so no branch makes the compiler wait for
+// loads in flight.  Each wave reduces its own partials (no cross-wave sum is
+// needed).
 // ---------------------------------------------------------------------------
-template <typename T, int CA, int KZ>
+template <typename T, int CAW, int KZ>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(
     const T* __restrict__ X, long long ldx, int ncx, const T* __restrict__ Z1, long long ldz1,
     int nz1, const T* __restrict__ Z2, long long ldz2, int nz2, long long N, long long chunk,
     int nct, double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    constexpr int PPT = 16 / sizeof(T);  // points per thread per step (one 16-byte load)
-    constexpr int STEP = PPT * kThreads;
-    __shared__ double lds[4 * CA * KZ];
+    constexpr int PPT = 16 / sizeof(T);  // points per lane per step (one 16-byte load)
+    constexpr int STEP = 64 * PPT;       // points per step (all four waves share them)
+    constexpr int NSL = (KZ * 64 + kThreads - 1) / kThreads;  // Z slots per thread
+    typedef T vt __attribute__((ext_vector_type(PPT)));
+    // three Z tiles: step s is read from tile s mod 3 while step s+2 is written
+    __shared__ vt zs[3][NSL * kThreads];
     const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
     const int ct = b % nct;
     const long long ch = b / nct;
     const long long p0 = ch * chunk;
     const long long p1 = (p0 + chunk < N) ? p0 + chunk : N;
-    const int c0 = ct * CA;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c0 = ct * 4 * CAW + wave * CAW;
     const int nz = nz1 + nz2;
-    double acc[CA][KZ];
-#pragma unroll
-    for (int a = 0; a < CA; ++a)
-#pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = 0.0;
     // columns beyond ncx / nz alias valid ones; their sums are discarded
-    const T* zc[KZ];
+    const T* xc[CAW];
 #pragma unroll
-    for (int jz = 0; jz < KZ; ++jz) {
-        const int j = jz < nz ? jz : nz - 1;
-        zc[jz] = j < nz1 ? Z1 + j * ldz1 : Z2 + (j - nz1) * ldz2;
+    for (int a = 0; a < CAW; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : ncx - 1) * ldx;
+    // this thread's Z slots: slot q holds lane q%64's points of column q/64
+    // (slots past KZ*64 load a valid column into the tile's padding)
+    const T* zq[NSL];
+#pragma unroll
+    for (int i = 0; i < NSL; ++i) {
+        const int q = threadIdx.x + kThreads * i;
+        const int j0 = q / 64;
+        const int j = j0 < nz ? j0 : nz - 1;
+        zq[i] = (j < nz1 ? Z1 + (long long)j * ldz1 : Z2 + (long long)(j - nz1) * ldz2) +
+                (q % 64) * PPT;
     }
-    const T* xc[CA];
+    double acc[CAW][KZ];
 #pragma unroll
-    for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : ncx - 1) * ldx;
+    for (int a = 0; a < CAW; ++a)
+#pragma unroll
+        for (int j = 0; j < KZ; ++j) acc[a][j] = 0.0;
 
-    // full vectors (chunk starts are multiples of 512 points)
-    const long long pv1 = p0 + (p1 - p0) / PPT * PPT;
-    long long p = p0 + (long long)PPT * threadIdx.x;
-    T zn[KZ][PPT], xn[CA][PPT];
-    if (p < pv1) {
+    const long long nstep = (p1 - p0) / STEP;
+    if (nstep > 0) {
+        auto at = [&](long long st) { return p0 + (st < nstep ? st : nstep - 1) * STEP; };
+        // Step st: issue X(st+1) and Z(st+2), run the FMAs of step st on X
+        // registers and Z tile st mod 3, then store the Z registers loaded at
+        // step st-1 into tile (st+1) mod 3 (last read at step st-2) and
+        // synchronise.  The loop is unrolled by two with named register sets,
+        // so every value is loaded in one half and consumed in the other
+        // (no copies of loaded registers that would wait for the loads).
+        auto half = [&](long long st, vt (&xcur)[CAW], vt (&xnext)[CAW], vt (&zload)[NSL],
+                        const vt (&zstore)[NSL]) {
+            const long long px = at(st + 1) + lane * PPT, pz = at(st + 2);
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) load_pts<T, PPT, false>(zc[jz] + p, zn[jz]);
+            for (int a = 0; a < CAW; ++a)
+                xnext[a] = __builtin_nontemporal_load(reinterpret_cast<const vt*>(xc[a] + px));
 #pragma unroll
-        for (int a = 0; a < CA; ++a) load_pts<T, PPT, true>(xc[a] + p, xn[a]);
-    }
-    for (; p < pv1; p += STEP) {
-        T zv[KZ][PPT], xv[CA][PPT];
+            for (int i = 0; i < NSL; ++i) zload[i] = *reinterpret_cast<const vt*>(zq[i] + pz);
+            __builtin_amdgcn_sched_barrier(0);  // the loads go out before the FMAs
+            const vt* zt = zs[st % 3];
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz)
+            for (int j = 0; j < KZ; ++j) {
+                const vt zv = zt[j * 64 + lane];
 #pragma unroll
-            for (int e = 0; e < PPT; ++e) zv[jz][e] = zn[jz][e];
+                for (int a = 0; a < CAW; ++a)
 #pragma unroll
-        for (int a = 0; a < CA; ++a)
+                    for (int e = 0; e < PPT; ++e)
+                        acc[a][j] = fma((double)xcur[a][e], (double)zv[e], acc[a][j]);
+            }
+            vt* zw = zs[(st + 1) % 3];
 #pragma unroll
-            for (int e = 0; e < PPT; ++e) xv[a][e] = xn[a][e];
-        const long long pn = p + STEP;
-        if (pn < pv1) {
+            for (int i = 0; i < NSL; ++i) zw[threadIdx.x + kThreads * i] = zstore[i];
+            __syncthreads();
+        };
+        vt xa[CAW], xb[CAW], za[NSL], zb[NSL];
 #pragma unroll
-            for (int jz = 0; jz < KZ; ++jz) load_pts<T, PPT, false>(zc[jz] + pn, zn[jz]);
-#pragma unroll
-            for (int a = 0; a < CA; ++a) load_pts<T, PPT, true>(xc[a] + pn, xn[a]);
+        for (int i = 0; i < NSL; ++i) {
+            zs[0][threadIdx.x + kThreads * i] = *reinterpret_cast<const vt*>(zq[i] + at(0));
+            zb[i] = *reinterpret_cast<const vt*>(zq[i] + at(1));
         }
 #pragma unroll
-        for (int a = 0; a < CA; ++a)
-#pragma unroll
-            for (int jz = 0; jz < KZ; ++jz)
-#pragma unroll
-                for (int e = 0; e < PPT; ++e)
-                    acc[a][jz] = fma((double)xv[a][e], (double)zv[jz][e], acc[a][jz]);
+        for (int a = 0; a < CAW; ++a)
+            xa[a] = __builtin_nontemporal_load(reinterpret_cast<const vt*>(xc[a] + at(0) + lane * PPT));
+        __syncthreads();
+        long long st = 0;
+        for (; st + 2 <= nstep; st += 2) {
+            half(st, xa, xb, za, zb);
+            half(st + 1, xb, xa, zb, za);
+        }
+        if (st < nstep) half(st, xa, xb, za, zb);
     }
-    for (long long q = pv1 + threadIdx.x; q < p1; q += kThreads) {  // ragged tail
-        double z0[KZ];
+    // ragged tail of the chunk: lanes over points, Z read directly
+    for (long long q = p0 + nstep * STEP + lane; q < p1; q += 64) {
+        double xq[CAW];
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) z0[jz] = to_f64(zc[jz][q]);
+        for (int a = 0; a < CAW; ++a) xq[a] = to_f64(xc[a][q]);
 #pragma unroll
-        for (int a = 0; a < CA; ++a) {
-            const double x0 = to_f64(xc[a][q]);
+        for (int j = 0; j < KZ; ++j) {
+            const int jj = j < nz ? j : nz - 1;
+            const T* zc = jj < nz1 ? Z1 + (long long)jj * ldz1 : Z2 + (long long)(jj - nz1) * ldz2;
+            const double zv = to_f64(zc[q]);
 #pragma unroll
-            for (int jz = 0; jz < KZ; ++jz) acc[a][jz] = fma(x0, z0[jz], acc[a][jz]);
+            for (int a = 0; a < CAW; ++a) acc[a][j] = fma(xq[a], zv, acc[a][j]);
         }
     }
-    double flat[CA * KZ], outv[CA * KZ];
 #pragma unroll
-    for (int a = 0; a < CA; ++a)
+    for (int a = 0; a < CAW; ++a)
 #pragma unroll
-        for (int jz = 0; jz < KZ; ++jz) flat[a * KZ + jz] = acc[a][jz];
-    block_sum<CA * KZ>(flat, lds, outv);
-    for (int k = threadIdx.x; k < CA * KZ; k += kThreads) {
-        const int a = k / KZ, jz = k % KZ;
-        if (c0 + a < ncx && jz < nz) part[(ch * ncx + c0 + a) * KZ + jz] = outv[k];
-    }
+        for (int j = 0; j < KZ; ++j) {
+            const double t = wave_sum(acc[a][j]);
+            if (lane == 0 && c0 + a < ncx && j < nz) part[(ch * ncx + c0 + a) * KZ + j] = t;
+        }
 }
 
 // Block Gram, stage 2: G[c*nz + j] = sum over chunks in a fixed order.

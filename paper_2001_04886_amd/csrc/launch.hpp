@@ -424,7 +424,8 @@ inline void launch_residual(Ctx& c, const StencilView& v, const double* f, const
 }
 
 // Gram geometry: column-tile width for a given Z width, and the point chunk.
-constexpr int gram_ca_c(int kz) { return kz <= 9 ? 8 : 4; }
+// X columns per wave of the Gram kernel (a workgroup takes 4 waves' worth)
+constexpr int gram_ca_c(int kz) { return kz <= 9 ? 4 : 2; }
 inline int gram_ca(int kz) { return gram_ca_c(kz); }
 inline int gram_kz(int nz) {
     static const int ks[] = {1, 2, 4, 8, 9, 12, 13, 16, 17};
@@ -436,7 +437,7 @@ inline void gram_geometry(long long N, int ncx, int nz, int* KZ, int* CA, int* n
                           long long* chunk) {
     *KZ = gram_kz(nz);
     *CA = gram_ca(*KZ);
-    *nct = (ncx + *CA - 1) / *CA;
+    *nct = (ncx + 4 * *CA - 1) / (4 * *CA);
     long long nch = std::min<long long>((N + 8191) / 8192, std::max(1, 2048 / *nct));
     nch = std::max<long long>(1, std::min<long long>(nch, 512));
     long long ck = round_up((N + nch - 1) / nch, 512);
