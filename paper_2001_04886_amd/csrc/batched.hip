@@ -350,64 +350,118 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
     return nacc;
 }
 
-// out[a * nz + j] = sum_{p in R} X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ):
-// tiles of CA columns of X against all of Z, point pairs per thread, one
-// workgroup reduction per tile.  Columns past ncx / nz are clamped to valid
-// ones and their sums dropped.
-template <int NT, int CA, int KZ>
+// out[a * nz + j] = sum_{p in R} X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ).
+// The waves of the workgroup walk the same 128 points per step, wave w taking
+// CAW columns of X in the current pass (CAW = 4, or 2 for KZ > 5 to bound the
+// registers; CAW NT/64 columns per pass).  The step's Z tile (KZ columns x 64 lanes x 16 bytes) is loaded once
+// for the workgroup, two steps ahead, into a three-deep LDS ring (ztile: 3
+// tiles of KZ*64 + 1 pairs; the extra pair takes the loads of threads without a
+// tile slot), so Z is read once per pass rather than once per few columns of
+// X.  The step loop is unrolled by two with named register sets and every load
+// in it is unconditional (addresses past the range clamp to its last step).
+// Each wave reduces its own columns.  Columns past ncx / nz are clamped to
+// valid ones and their sums dropped.
+template <int NT, int KZ>
 __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z, long long ldz,
-                        int nz, const Range& R, double* out /* [ncx][nz] */, double* red) {
-    const double* zc[KZ];
+                        int nz, const Range& R, double* out /* [ncx][nz] */, d2v* ztile) {
+    constexpr int CAW = KZ <= 5 ? 4 : 2, STEP = 128, TS = KZ * 64 + 1, NSL = (KZ * 64 + NT - 1) / NT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    SSTEP_LDS d2v* zt = (SSTEP_LDS d2v*)ztile;
+    const double* zq[NSL];
+    int zd[NSL];
 #pragma unroll
-    for (int j = 0; j < KZ; ++j) zc[j] = Z + (long long)(j < nz ? j : nz - 1) * ldz;
-    const long long pe = threadIdx.x == 0 ? R.e0 : (threadIdx.x == 1 ? R.e1 : -1);
-    for (int c0 = 0; c0 < ncx; c0 += CA) {
-        const double* xc[CA];
+    for (int i = 0; i < NSL; ++i) {
+        const int q = threadIdx.x + NT * i;
+        const bool slot = q < KZ * 64;
+        const int j0 = slot ? q / 64 : 0;
+        const int j = j0 < nz ? j0 : nz - 1;
+        zq[i] = Z + (long long)j * ldz + (slot ? (q % 64) * 2 : 0);
+        zd[i] = slot ? q : KZ * 64;
+    }
+    const long long nstep = (R.pb - R.pa) / STEP;
+    auto at = [&](long long st) { return R.pa + (st < nstep ? st : nstep - 1) * STEP; };
+    for (int c0 = 0; c0 < ncx; c0 += (NT / 64) * CAW) {
+        const int cw = c0 + wave * CAW;
+        const double* xc[CAW];
 #pragma unroll
-        for (int a = 0; a < CA; ++a) xc[a] = X + (long long)(c0 + a < ncx ? c0 + a : ncx - 1) * ldx;
-        double acc[CA][KZ];
+        for (int a = 0; a < CAW; ++a) xc[a] = X + (long long)(cw + a < ncx ? cw + a : ncx - 1) * ldx;
+        double acc[CAW][KZ];
 #pragma unroll
-        for (int a = 0; a < CA; ++a)
+        for (int a = 0; a < CAW; ++a)
 #pragma unroll
             for (int j = 0; j < KZ; ++j) acc[a][j] = 0.0;
-        for (long long p = R.pa + 2 * threadIdx.x; p < R.pb; p += 2 * NT) {
-            d2v z[KZ], x[CA];
+        if (nstep > 0) {
+            // step st: issue X(st+1), Z(st+2); FMAs on X(st) and tile st mod 3;
+            // store the Z loaded at step st-1 into tile (st+1) mod 3 (last read
+            // at step st-2); barrier
+            auto half = [&](long long st, d2v (&xcur)[CAW], d2v (&xnext)[CAW], d2v (&zload)[NSL],
+                            const d2v (&zstore)[NSL]) {
+                const long long px = at(st + 1) + 2 * lane, pz = at(st + 2);
 #pragma unroll
-            for (int j = 0; j < KZ; ++j) z[j] = ld2(zc[j] + p);
+                for (int a = 0; a < CAW; ++a) xnext[a] = ld2(xc[a] + px);
 #pragma unroll
-            for (int a = 0; a < CA; ++a) x[a] = ld2(xc[a] + p);
+                for (int i = 0; i < NSL; ++i) zload[i] = ld2(zq[i] + pz);
+                __builtin_amdgcn_sched_barrier(0);  // the loads go out before the FMAs
+                const SSTEP_LDS d2v* tile = zt + (int)(st % 3) * TS;
 #pragma unroll
-            for (int a = 0; a < CA; ++a)
+                for (int j = 0; j < KZ; ++j) {
+                    const d2v zv = tile[j * 64 + lane];
 #pragma unroll
-                for (int j = 0; j < KZ; ++j)
-                    acc[a][j] = fma(x[a].y, z[j].y, fma(x[a].x, z[j].x, acc[a][j]));
+                    for (int a = 0; a < CAW; ++a)
+                        acc[a][j] = fma(xcur[a].y, zv.y, fma(xcur[a].x, zv.x, acc[a][j]));
+                }
+                SSTEP_LDS d2v* w = zt + (int)((st + 1) % 3) * TS;
+#pragma unroll
+                for (int i = 0; i < NSL; ++i) w[zd[i]] = zstore[i];
+                __syncthreads();
+            };
+            d2v xa[CAW], xb[CAW], za[NSL], zb[NSL];
+#pragma unroll
+            for (int i = 0; i < NSL; ++i) {
+                zt[zd[i]] = ld2(zq[i] + at(0));
+                zb[i] = ld2(zq[i] + at(1));
+            }
+#pragma unroll
+            for (int a = 0; a < CAW; ++a) xa[a] = ld2(xc[a] + at(0) + 2 * lane);
+            __syncthreads();
+            long long st = 0;
+            for (; st + 2 <= nstep; st += 2) {
+                half(st, xa, xb, za, zb);
+                half(st + 1, xb, xa, zb, za);
+            }
+            if (st < nstep) half(st, xa, xb, za, zb);
         }
-        if (pe >= 0) {
+        // pairs after the last whole step, then the (at most two) single points
+        for (long long p = R.pa + nstep * STEP + 2 * lane; p < R.pb; p += STEP) {
+            d2v x[CAW];
 #pragma unroll
-            for (int a = 0; a < CA; ++a) {
-                const double xv = ldg(xc[a] + pe);
+            for (int a = 0; a < CAW; ++a) x[a] = ld2(xc[a] + p);
 #pragma unroll
-                for (int j = 0; j < KZ; ++j) acc[a][j] = fma(xv, ldg(zc[j] + pe), acc[a][j]);
+            for (int j = 0; j < KZ; ++j) {
+                const d2v zv = ld2(Z + (long long)(j < nz ? j : nz - 1) * ldz + p);
+#pragma unroll
+                for (int a = 0; a < CAW; ++a)
+                    acc[a][j] = fma(x[a].y, zv.y, fma(x[a].x, zv.x, acc[a][j]));
             }
         }
-        // workgroup reduction of the CA*KZ sums (wave shuffles, then LDS)
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        __syncthreads();
+        const long long pe = lane == 0 ? R.e0 : (lane == 1 ? R.e1 : -1);
+        if (pe >= 0) {
 #pragma unroll
-        for (int a = 0; a < CA; ++a)
+            for (int a = 0; a < CAW; ++a) {
+                const double xv = ldg(xc[a] + pe);
+#pragma unroll
+                for (int j = 0; j < KZ; ++j)
+                    acc[a][j] = fma(xv, ldg(Z + (long long)(j < nz ? j : nz - 1) * ldz + pe), acc[a][j]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < CAW; ++a)
 #pragma unroll
             for (int j = 0; j < KZ; ++j) {
                 const double t = wave_sum(acc[a][j]);
-                if (lane == 0) red[wave * CA * KZ + a * KZ + j] = t;
+                if (lane == 0 && cw + a < ncx && j < nz) out[(cw + a) * nz + j] = t;
             }
-        __syncthreads();
-        for (int k = threadIdx.x; k < CA * KZ; k += NT) {
-            const int a = k / KZ, j = k % KZ;
-            double t = 0.0;
-            for (int w = 0; w < NT / 64; ++w) t += red[w * CA * KZ + k];
-            if (c0 + a < ncx && j < nz) out[(c0 + a) * nz + j] = t;
-        }
-        __syncthreads();
+        __syncthreads();  // the next pass rewrites tiles 0 and 1
     }
 }
 
@@ -489,6 +543,7 @@ __device__ __noinline__ void scalar_ysolve(BatchSlot& W, int ncols, int s, int l
 // LDS state of a workgroup handed to the solve.
 struct WgShared {
     double* red;
+    d2v* ztile;  // Z tiles of the block Gram: 3 x ((KZ + 1) * 64 + 1) pairs
     double* sh;
     double* lw;
     GramFactor* lf;
@@ -511,6 +566,7 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
     const long long r0 = rows * tm.rank / tm.T, r1 = rows * (tm.rank + 1) / tm.T;
     const Range R(r0 * A.nx, r1 * A.nx);
     double* red = L.red;
+    d2v* ztile = L.ztile;
     double* sh = L.sh;
     double* lm = L.lm;
 
@@ -561,7 +617,7 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             if (kb > 0) {
                 // C = V_prev^T [y_1..y_s]
                 double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
-                wg_gram<NT, CA, KZ>(V, ld, c0, Yk + ld, ld, s, R, gout, red);
+                wg_gram<NT, KZ>(V, ld, c0, Yk + ld, ld, s, R, gout, ztile);
                 if (tm.T > 1) team_combine<NT>(tm, W, c0 * s, W.C);
                 pc.lap(SSTEP_K_GRAM);
                 // T_i = W_i^{-1} C_i, update coefficients
@@ -587,7 +643,7 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             // block Gram of [w_k, y_1..y_s]
             {
                 double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
-                wg_gram<NT, CA, KZ + 1>(Yk, ld, s1, Yk, ld, s1, R, gout, red);
+                wg_gram<NT, KZ + 1>(Yk, ld, s1, Yk, ld, s1, R, gout, ztile);
                 if (tm.T > 1) team_combine<NT>(tm, W, s1 * s1, W.C);
             }
             pc.lap(SSTEP_K_GRAM);
@@ -688,7 +744,8 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
 
 template <int NT, int CA, int KZ>
 __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
-    __shared__ double red[(NT / 64) * CA * (KZ + 1)];
+    __shared__ double red[NT / 64];
+    __shared__ d2v ztile[3 * ((KZ + 1) * 64 + 1)];
     __shared__ double sh[3 * kMaxS + 4];
     __shared__ double lw[kMaxS * kMaxS];
     __shared__ GramFactor lf;
@@ -698,7 +755,17 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
     __shared__ long long clk[SSTEP_K_NCLASS + 1];
     __shared__ Team tm;
     __shared__ int next;
-    const WgShared L{red, sh, lw, &lf, lm, l1, clk};
+    // filled member by member: a braced initializer of LDS addresses would be
+    // folded into a static initializer the compiler cannot emit
+    WgShared L;
+    L.red = red;
+    L.ztile = ztile;
+    L.sh = sh;
+    L.lw = lw;
+    L.lf = &lf;
+    L.lm = lm;
+    L.l1 = l1;
+    L.clk = clk;
     BatchSlot& W = args.slots[blockIdx.x];
     int* abort = args.queue + 2;
 
