@@ -92,7 +92,11 @@ def test_matrix_powers_match_oracle(basis, ndim, shape, s):
 
 
 @pytest.mark.parametrize("N,ncx,ncz", [(1, 1, 1), (1000, 7, 3), (4097, 40, 8), (65536 + 513, 64, 9),
-                                       (300001, 17, 16), (1024 * 1024 + 5, 40, 8)])
+                                       (300001, 17, 16), (1024 * 1024 + 5, 40, 8),
+                                       # every Z width class, chunks shorter than one step,
+                                       # ragged column groups of the shared-Z kernel
+                                       (127, 3, 8), (130, 5, 4), (5000, 20, 2), (70001, 33, 12),
+                                       (123457, 18, 13), (262147, 50, 16)])
 def test_block_gram_matches_numpy(N, ncx, ncz):
     rng = np.random.default_rng(N)
     ld = (N + 63) // 64 * 64
@@ -115,7 +119,7 @@ def test_block_gram_matches_numpy(N, ncx, ncz):
                                   (300001, 4), (1024 * 1024 + 5, 9), (2 << 20, 7), (77777, 13)])
 def test_block_self_gram_matches_numpy(N, nc):
     # X^T X of one block (the one-pass symmetric kernel for <= 9 columns, the
-    # tiled one beyond): symmetric to the bit, within the summation bound
+    # general block Gram beyond): symmetric to the bit, within the summation bound
     rng = np.random.default_rng(N + 7 * nc)
     ld = (N + 63) // 64 * 64
     X = torch.zeros((nc, ld), dtype=torch.float64, device=DEV)
