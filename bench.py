@@ -563,11 +563,12 @@ def bench_learned(args):
     dev = torch.device("cuda:0")
     params, out_scale, meta = LN.load_model()
     log = lambda *a: print("#", *a, file=sys.stderr, flush=True)  # noqa: E731
+    factor, sweeps = int(meta["coarsen"]), int(meta["sweeps"])
     if args.warmup:
         wds = LN.generate(1, 9000, nstreams=1, log=log)
-        LN.evaluate(params, out_scale, wds, log=log)
+        LN.evaluate(params, out_scale, wds, factor, sweeps, log=log)
     ds = LN.generate(args.eval_samples, 5000, nstreams=1, log=log)
-    res = LN.evaluate(params, out_scale, ds, log=log)
+    res = LN.evaluate(params, out_scale, ds, factor, sweeps, log=log)
     summ = {}
     for mode in ("zero", "cnn", "cnn_nofallback"):
         r = res[mode]
@@ -619,12 +620,14 @@ def bench_learned(args):
           v, "s", False, v * 1e3, args, "f64+bf16",
           f"2-D 5-pt -div(k grad u)=f, 256^2, log k and f squared-exponential GRFs (length 0.1), "
           f"{args.eval_samples} held-out seeds; s-GMRES(m=30, s=8) FP64 tol 1e-8; network 2-32-32-32-1 "
-          f"dilated 3x3, bf16 storage / FP32 accumulation, trained on {meta.get('samples')} solved "
-          f"systems x 8 grid symmetries",
+          f"dilated 3x3, bf16 storage / FP32 accumulation, on {factor}x{factor} block averages "
+          f"(bilinear interpolation, {sweeps} Jacobi sweeps), trained on {meta.get('samples')} "
+          f"solved systems x 8 grid symmetries",
           {"results": summ, "fallback_rate": fb,
            "blocks_ratio_nofallback": summ["cnn_nofallback"]["mean_blocks"] / summ["zero"]["mean_blocks"],
            "time_ratio_vs_zero": v / summ["zero"]["mean_s"],
-           "model": {k: meta.get(k) for k in ("samples", "epochs", "batch", "lr", "steps")},
+           "model": {k: meta.get(k) for k in ("samples", "epochs", "batch", "lr", "steps",
+                                                "coarsen", "sweeps")},
            "cnn": {"forward_ms_batch32": fwd_ms, "gradient_ms_batch32": grad_ms,
                    "forward_TFLOPs": tf_fwd, "gradient_TFLOPs": tf_grad},
            "roofline": {"bound": "mfma", "kernel": "network forward, batch 32 (all layers)",

@@ -296,6 +296,36 @@ int sstep_x0_predict(const float *params, double out_scale, const sstep_stencil 
                      const float *logk, const double *f, double *x0, int use_fallback,
                      int *used_fallback, const sstep_options *opt);
 
+/* Block averages: out[b][J][I] = mean of the factor x factor block of
+ * in[b][ny][nx] with corner (factor J, factor I); sums in FP64.  in, out
+ * DEVICE doubles, out [batch][ny/factor][nx/factor]; nx and ny must be
+ * multiples of factor (else SSTEP_ERR_ARG).  Enqueued on stream; returns after
+ * completion.  (Used to build the coarse inputs and targets of the network
+ * below from fine-grid data.) */
+int sstep_grid_pool(const double *in, double *out, int batch, int nx, int ny, int factor,
+                    void *stream);
+
+/* Coarse-grid initial guess for one 2-D system A x = f on an nx x ny grid
+ * (nx, ny multiples of factor).  log k and f are block-averaged over
+ * factor x factor cells (as sstep_grid_pool; log k summed in FP64, stored as
+ * float); the network above runs on the (ny/factor) x (nx/factor) coarse grid,
+ * where its receptive field of 31 points spans a factor-times larger part of
+ * the domain; its guess (out * rms(pooled f) * out_scale) is interpolated
+ * bilinearly onto the fine grid, coarse values sitting at the block centres
+ * (fine point i at coarse coordinate (i + 1/2)/factor - 1/2, clamped to the
+ * coarse grid); then `sweeps` damped Jacobi sweeps x += 0.8 (f - A x)/diag(A)
+ * remove the interpolation's high-frequency error; then the fallback test of
+ * sstep_x0_predict if use_fallback != 0.  params / out_scale: a model trained
+ * on block-averaged data of the same factor.  Workspace: opt->workspace of at
+ * least sstep_x0_coarse_workspace_bytes(nx, ny, factor) bytes or NULL.
+ * Errors as sstep_x0_predict; factor < 1, nx or ny not a multiple of factor,
+ * or sweeps outside 0..100000 give SSTEP_ERR_ARG. */
+size_t sstep_x0_coarse_workspace_bytes(int nx, int ny, int factor);
+int sstep_x0_predict_coarse(const float *params, double out_scale, int factor, int sweeps,
+                            const sstep_stencil *A, const float *logk, const double *f,
+                            double *x0, int use_fallback, int *used_fallback,
+                            const sstep_options *opt);
+
 #ifdef __cplusplus
 }
 #endif

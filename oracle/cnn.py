@@ -165,6 +165,74 @@ def predict_x0(params, out_scale, logk, f):
     return out * (fr * out_scale)[:, None, None]
 
 
+# Coarse-grid guess -----------------------------------------------------------
+#
+# The network above sees 31 points in each direction.  For the coarse-grid
+# guess it runs on block averages of the inputs (factor x factor cells), and
+# its guess is carried back to the fine grid by bilinear interpolation and
+# smoothed by damped Jacobi sweeps with the fine-grid operator.
+
+def pool(x, factor):
+    """Block averages: x [B][ny][nx] (or [ny][nx]) -> [B][ny/factor][nx/factor];
+    entry (J, I) is the mean of the factor x factor block with corner
+    (factor J, factor I)."""
+    x = np.asarray(x, dtype=np.float64)
+    two_d = x.ndim == 2
+    if two_d:
+        x = x[None]
+    B, ny, nx = x.shape
+    out = np.zeros((B, ny // factor, nx // factor))
+    for J in range(ny // factor):
+        for I in range(nx // factor):
+            blk = x[:, J * factor:(J + 1) * factor, I * factor:(I + 1) * factor]
+            out[:, J, I] = blk.sum(axis=(1, 2)) / (factor * factor)
+    return out[0] if two_d else out
+
+
+def upsample(xc, factor):
+    """Bilinear interpolation of the coarse field xc [nyc][nxc], whose values
+    sit at the centres of factor x factor blocks, onto the fine grid: fine
+    index i sits at coarse coordinate (i + 1/2)/factor - 1/2; the two coarse
+    neighbours used are clamped into the coarse grid."""
+    xc = np.asarray(xc, dtype=np.float64)
+    nyc, nxc = xc.shape
+
+    def axis(nc):
+        u = (np.arange(nc * factor) + 0.5) / factor - 0.5
+        lo = np.floor(u)
+        t = u - lo
+        lo = lo.astype(np.int64)
+        return np.clip(lo, 0, nc - 1), np.clip(lo + 1, 0, nc - 1), t
+
+    ia, ib, tx = axis(nxc)
+    ja, jb, ty = axis(nyc)
+    rows_a = (1.0 - tx)[None, :] * xc[ja][:, ia] + tx[None, :] * xc[ja][:, ib]
+    rows_b = (1.0 - tx)[None, :] * xc[jb][:, ia] + tx[None, :] * xc[jb][:, ib]
+    return (1.0 - ty)[:, None] * rows_a + ty[:, None] * rows_b
+
+
+def jacobi(A, f, x, sweeps, omega=0.8):
+    """Damped Jacobi sweeps x <- x + omega (f - A x) / diag(A) on the oracle
+    operator A (flat vectors)."""
+    import oracle as O
+    d = A.coef[0] if A.coef is not None else np.full(A.N, A.c[0])
+    x = np.array(x, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    for _ in range(sweeps):
+        x = x + omega * (f - O.apply(A, x)) / d
+    return x
+
+
+def predict_x0_coarse(params, out_scale, factor, sweeps, A, logk, f):
+    """Coarse-grid guess for one [ny][nx] sample (flat result): block-averaged
+    log k (stored in float32, as the network input is) and f, the network's
+    guess on the coarse grid, bilinear interpolation, Jacobi sweeps."""
+    logk_c = pool(logk, factor).astype(np.float32).astype(np.float64)
+    f_c = pool(f, factor)
+    xc = predict_x0(params, out_scale, logk_c[None], f_c[None])[0]
+    return jacobi(A, np.asarray(f, dtype=np.float64).ravel(), upsample(xc, factor).ravel(), sweeps)
+
+
 def target(x, f, out_scale):
     """Normalised regression target x / (rms(f) * out_scale)."""
     return np.asarray(x, dtype=np.float64) / (rms(f) * out_scale)[:, None, None]

@@ -654,6 +654,73 @@ __global__ __launch_bounds__(kThreads) void k_fallback_apply(long long n, const 
 }
 
 // ---------------------------------------------------------------------------
+// coarse-grid guess: block averages, bilinear upsampling, damped Jacobi
+// ---------------------------------------------------------------------------
+
+// out[b][J][I] = mean of the fac x fac block of in[b] whose corner is
+// (fac J, fac I); sums in FP64, rows of the block in order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pool(long long nout, int nx, int nxc, int nyc, int fac,
+                                                   const T* __restrict__ in, T* __restrict__ out) {
+    const long long hwc = (long long)nxc * nyc;
+    for (long long o = (long long)blockIdx.x * kThreads + threadIdx.x; o < nout;
+         o += (long long)gridDim.x * kThreads) {
+        const long long b = o / hwc, r = o - b * hwc;
+        const int J = (int)(r / nxc), I = (int)(r - (long long)J * nxc);
+        const T* src = in + b * hwc * fac * fac + ((long long)J * fac) * nx + (long long)I * fac;
+        double sum = 0.0;
+        for (int jj = 0; jj < fac; ++jj)
+            for (int ii = 0; ii < fac; ++ii) sum += (double)src[(long long)jj * nx + ii];
+        out[o] = (T)(sum / ((double)fac * fac));
+    }
+}
+
+// Bilinear interpolation of the coarse field xc [nyc][nxc] (values at the
+// centres of the fac x fac blocks) onto the fine grid [ny][nx]: fine point i
+// sits at coarse coordinate (i + 1/2)/fac - 1/2; indices outside the coarse
+// grid clamp to its edge.
+__global__ __launch_bounds__(kThreads) void k_upsample(long long n, int nx, int nxc, int nyc, int fac,
+                                                       const double* __restrict__ xc,
+                                                       double* __restrict__ x) {
+    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < n;
+         p += (long long)gridDim.x * kThreads) {
+        const int j = (int)(p / nx), i = (int)(p - (long long)j * nx);
+        const double u = (i + 0.5) / fac - 0.5, w = (j + 0.5) / fac - 0.5;
+        const double fu = floor(u), fw = floor(w);
+        const double tx = u - fu, ty = w - fw;
+        const int i0 = (int)fu, j0 = (int)fw;
+        const int ia = min(max(i0, 0), nxc - 1), ib = min(max(i0 + 1, 0), nxc - 1);
+        const int ja = min(max(j0, 0), nyc - 1), jb = min(max(j0 + 1, 0), nyc - 1);
+        const double lo = (1.0 - tx) * xc[(long long)ja * nxc + ia] + tx * xc[(long long)ja * nxc + ib];
+        const double hi = (1.0 - tx) * xc[(long long)jb * nxc + ia] + tx * xc[(long long)jb * nxc + ib];
+        x[p] = (1.0 - ty) * lo + ty * hi;
+    }
+}
+
+// One damped Jacobi sweep on the 2-D five-point system:
+// xout = xin + omega (f - A xin) / diag(A).
+__global__ __launch_bounds__(kThreads) void k_jacobi(StencilView A, const double* __restrict__ f,
+                                                     const double* __restrict__ xin,
+                                                     double* __restrict__ xout, double omega) {
+    const int nx = A.nx, ny = A.ny;
+    const long long n = (long long)nx * ny;
+    for (long long p = (long long)blockIdx.x * kThreads + threadIdx.x; p < n;
+         p += (long long)gridDim.x * kThreads) {
+        const int j = (int)(p / nx), i = (int)(p - (long long)j * nx);
+        double c[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) c[q] = A.coef ? A.coef[q * A.N + p] : A.c[q];
+        double ax = 0.0;
+        if (i > 0) ax += c[1] * xin[p - 1];
+        if (i < nx - 1) ax += c[2] * xin[p + 1];
+        if (j > 0) ax += c[3] * xin[p - nx];
+        if (j < ny - 1) ax += c[4] * xin[p + nx];
+        ax += c[0] * xin[p];
+        xout[p] = xin[p] + omega * (f[p] - ax) / c[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -758,6 +825,38 @@ inline Bufs bufs(char* ws, const Layout& L, bool training, bool fallback) {
         b.flag = (int*)(ws + L.flag);
     }
     return b;
+}
+
+// Workspace of the coarse-grid guess: the network's forward pass on the
+// coarse grid, the pooled inputs and the coarse guess, one fine vector for the
+// Jacobi sweeps, and the fine-grid fallback test (residual and partials).
+struct CoarseLayout {
+    Layout net;  // offsets relative to `net_at`
+    size_t net_at, logk_c, f_c, x_c, tmp, r, rpart, fpart, flag, total;
+};
+
+inline CoarseLayout coarse_layout(int nx, int ny, int fac) {
+    const int nxc = nx / fac, nyc = ny / fac;
+    const long long nc = (long long)nxc * nyc, n = (long long)nx * ny;
+    CoarseLayout C{};
+    C.net = layout(1, nyc, nxc, false, false);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    C.net_at = take(C.net.total);
+    C.logk_c = take(4 * (size_t)nc);
+    C.f_c = take(8 * (size_t)nc);
+    C.x_c = take(8 * (size_t)nc);
+    C.tmp = take(8 * (size_t)n);
+    C.r = take(8 * (size_t)n);
+    C.rpart = take(8 * (size_t)ny * ((nx + kThreads - 1) / kThreads));
+    C.fpart = take(8 * 1024);
+    C.flag = take(16);
+    C.total = o;
+    return C;
 }
 
 inline unsigned pix_blocks(long long npix) { return (unsigned)((npix + kThreads - 1) / kThreads); }
@@ -1014,6 +1113,91 @@ int sstep_x0_predict(const float* params, double out_scale, const sstep_stencil*
             SSTEP_HIP(hipGetLastError());
             if (used_fallback)
                 SSTEP_HIP(hipMemcpyAsync(used_fallback, b.flag, 4, hipMemcpyDeviceToHost, st));
+        }
+        return SSTEP_OK;
+    });
+}
+
+int sstep_grid_pool(const double* in, double* out, int batch, int nx, int ny, int factor,
+                    void* stream) {
+    if (!in || !out || !dims_ok(batch, nx, ny) || factor < 1 || nx % factor || ny % factor)
+        return SSTEP_ERR_ARG;
+    return cnn_guard([&]() -> int {
+        const hipStream_t st = (hipStream_t)stream;
+        const int nxc = nx / factor, nyc = ny / factor;
+        const long long nout = (long long)batch * nxc * nyc;
+        hipLaunchKernelGGL(cnn::k_pool<double>, dim3(cnn::pix_blocks(nout)), dim3(kThreads), 0, st,
+                           nout, nx, nxc, nyc, factor, in, out);
+        SSTEP_HIP(hipGetLastError());
+        SSTEP_HIP(hipStreamSynchronize(st));
+        return SSTEP_OK;
+    });
+}
+
+size_t sstep_x0_coarse_workspace_bytes(int nx, int ny, int factor) {
+    if (!dims_ok(1, nx, ny) || factor < 1 || nx % factor || ny % factor) return 0;
+    return cnn::coarse_layout(nx, ny, factor).total;
+}
+
+int sstep_x0_predict_coarse(const float* params, double out_scale, int factor, int sweeps,
+                            const sstep_stencil* A, const float* logk, const double* f, double* x0,
+                            int use_fallback, int* used_fallback, const sstep_options* opt) {
+    if (used_fallback) *used_fallback = 0;
+    if (!A || A->ndim != 2 || !dims_ok(1, A->nx, A->ny) || !params || !logk || !f || !x0 ||
+        !(out_scale > 0.0) || !std::isfinite(out_scale) || factor < 1 || A->nx % factor ||
+        A->ny % factor || sweeps < 0 || sweeps > 100000)
+        return SSTEP_ERR_ARG;
+    if (!al16(params) || !al16(logk) || !al16(f) || !al16(x0) || (A->coef && !al16(A->coef)))
+        return SSTEP_ERR_ARG;
+    if (!A->coef)
+        for (int q = 0; q < 5; ++q)
+            if (!std::isfinite(A->c[q])) return SSTEP_ERR_ARG;
+    const int nx = A->nx, ny = A->ny, nxc = nx / factor, nyc = ny / factor;
+    const long long nc = (long long)nxc * nyc, n = (long long)nx * ny;
+    const cnn::CoarseLayout C = cnn::coarse_layout(nx, ny, factor);
+    return with_workspace(opt, C.total, [&](hipStream_t st, char* ws) {
+        float* logk_c = (float*)(ws + C.logk_c);
+        double* f_c = (double*)(ws + C.f_c);
+        double* x_c = (double*)(ws + C.x_c);
+        double* tmp = (double*)(ws + C.tmp);
+        hipLaunchKernelGGL(cnn::k_pool<float>, dim3(cnn::pix_blocks(nc)), dim3(kThreads), 0, st, nc,
+                           nx, nxc, nyc, factor, logk, logk_c);
+        hipLaunchKernelGGL(cnn::k_pool<double>, dim3(cnn::pix_blocks(nc)), dim3(kThreads), 0, st, nc,
+                           nx, nxc, nyc, factor, f, f_c);
+        SSTEP_HIP(hipGetLastError());
+        const cnn::Bufs b = cnn::bufs(ws + C.net_at, C.net, false, false);
+        cnn::forward(st, 1, nyc, nxc, params, logk_c, f_c, nullptr, out_scale, b, x_c);
+        hipLaunchKernelGGL(cnn::k_upsample, dim3(cnn::pix_blocks(n)), dim3(kThreads), 0, st, n, nx,
+                           nxc, nyc, factor, (const double*)x_c, x0);
+        SSTEP_HIP(hipGetLastError());
+        const StencilView v = make_view(*A);
+        // damped Jacobi sweeps, alternating between x0 and tmp
+        constexpr double kOmega = 0.8;
+        for (int k = 0; k < sweeps; ++k) {
+            const double* src = (k % 2 == 0) ? x0 : tmp;
+            double* dst = (k % 2 == 0) ? tmp : x0;
+            hipLaunchKernelGGL(cnn::k_jacobi, dim3(cnn::pix_blocks(n)), dim3(kThreads), 0, st, v, f,
+                               src, dst, kOmega);
+        }
+        SSTEP_HIP(hipGetLastError());
+        if (sweeps % 2 == 1)
+            SSTEP_HIP(hipMemcpyAsync(x0, tmp, 8 * (size_t)n, hipMemcpyDeviceToDevice, st));
+        if (use_fallback) {
+            Ctx c;
+            c.st = st;
+            double* r = (double*)(ws + C.r);
+            double* rpart = (double*)(ws + C.rpart);
+            double* fpart = (double*)(ws + C.fpart);
+            int* flag = (int*)(ws + C.flag);
+            launch_residual<double>(c, v, f, x0, r, rpart);
+            launch_norm2(c, v.N, f, fpart);
+            hipLaunchKernelGGL(cnn::k_fallback_decide, dim3(1), dim3(64), 0, st, (const double*)rpart,
+                               (int)stencil_blocks(v), (const double*)fpart, norm_blocks(v.N), flag);
+            hipLaunchKernelGGL(cnn::k_fallback_apply, dim3(norm_blocks(v.N)), dim3(kThreads), 0, st,
+                               v.N, (const int*)flag, x0);
+            SSTEP_HIP(hipGetLastError());
+            if (used_fallback)
+                SSTEP_HIP(hipMemcpyAsync(used_fallback, flag, 4, hipMemcpyDeviceToHost, st));
         }
         return SSTEP_OK;
     });

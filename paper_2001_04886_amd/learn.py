@@ -6,14 +6,21 @@ variable-coefficient diffusion family -div(k grad u) = f on a 256 x 256 grid,
 with log k and f squared-exponential Gaussian random fields (correlation
 length 0.1, unit variance), and measures what the guess buys the solver.
 
+The network sees 31 points in each direction, far less than the domain of a
+global elliptic problem, so it runs on a coarse grid: inputs and targets are
+block averages over COARSEN x COARSEN cells (32 x 32 coarse points for the
+256 x 256 grid, where 31 points span the domain), and the guess is carried
+back by bilinear interpolation and SWEEPS damped Jacobi sweeps
+(sstep_x0_predict_coarse).
+
 Everything numeric runs in the HIP library: the solves that produce the
-training targets (sstep_gmres_solve), the network's forward/backward/Adam
-(sstep_cnn_train_step) and the guess with its fallback test
-(sstep_x0_predict).  This module only generates seeded inputs (through
-problems.py), moves batches, and keeps the books.
+training targets (sstep_gmres_solve), the block averages (sstep_grid_pool),
+the network's forward/backward/Adam (sstep_cnn_train_step) and the guess with
+its fallback test (sstep_x0_predict_coarse).  This module only generates
+seeded inputs (through problems.py), moves batches, and keeps the books.
 
 Command line (on a GPU):
-    python -m paper_2001_04886_amd.learn --samples 2048 --epochs 40 --out model.npz
+    python -m paper_2001_04886_amd.learn --samples 2560 --epochs 300 --out model.npz
 """
 from __future__ import annotations
 
@@ -32,6 +39,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_MODEL = os.path.join(_HERE, "tuned", "x0_cnn.npz")
 GRID = 256
 CORR_LENGTH = 0.1
+COARSEN = 8
 SOLVE_S, SOLVE_M, SOLVE_TOL = 8, 30, 1e-8
 
 
@@ -134,6 +142,16 @@ def generate(count, seed, n=GRID, nstreams=4, device="cuda:0", log=_log):
     return Dataset(logk, f, x, blocks, secs, seed)
 
 
+def coarsen(ds, factor):
+    """The block-averaged dataset the network trains on (log k kept float32)."""
+    import torch
+    if factor == 1:
+        return ds
+    lk = S.grid_pool(ds.logk.double().contiguous(), factor).float().contiguous()
+    return Dataset(lk, S.grid_pool(ds.f, factor), S.grid_pool(ds.x, factor), ds.blocks,
+                   ds.seconds, ds.seed)
+
+
 def out_scale_of(ds, nsamp=64):
     """rms over samples of x / rms(f): the output scale that makes the
     regression target O(1) (a model constant)."""
@@ -219,54 +237,65 @@ def save_model(path, params, out_scale, meta):
 
 
 def load_model(path=DEFAULT_MODEL):
+    """params, out_scale, meta; meta["coarsen"] / meta["sweeps"] (1 / 0 when
+    absent) say how the guess is formed."""
     with np.load(path, allow_pickle=False) as z:
-        return z["params"].astype(np.float32), float(z["out_scale"]), json.loads(str(z["meta"]))
+        meta = json.loads(str(z["meta"]))
+        meta.setdefault("coarsen", 1)
+        meta.setdefault("sweeps", 0)
+        return z["params"].astype(np.float32), float(z["out_scale"]), meta
 
 
-def evaluate(params, out_scale, ds, nstreams=1, log=_log):
-    """Solve every sample of ``ds`` from x0 = 0, from the network's guess with
-    the fallback rule, and from the raw guess; returns per-sample blocks and
-    wall seconds (guess included) for each, and the fallback flags."""
+def evaluate(params, out_scale, ds, factor=1, sweeps=0, nstreams=1, log=_log, modes=None):
+    """Solve every sample of ``ds`` from x0 = 0, from the network's guess
+    (block averages over ``factor`` cells, ``sweeps`` Jacobi sweeps) with the
+    fallback rule, and from the raw guess; returns per-sample blocks and wall
+    seconds (guess included) for each, and the fallback flags."""
     import torch
     dev = ds.logk.device
     n = ds.logk.shape[1]
     pdev = torch.as_tensor(params, device=dev)
     count = len(ds)
-    ws = [torch.empty(S.cnn_workspace_bytes(1, n, n, False), dtype=torch.uint8, device=dev)
+    ws = [torch.empty(S.x0_coarse_workspace_bytes(n, n, factor), dtype=torch.uint8, device=dev)
           for _ in range(nstreams)]
     fallback = np.zeros(count, dtype=bool)
     res = {}
-    for mode in ("zero", "cnn", "cnn_nofallback"):
+    for mode in modes or ("zero", "cnn", "cnn_nofallback"):
         x = torch.zeros_like(ds.f)
 
         def x0_fn(i, A, st, mode=mode):
             if mode == "zero":
                 return
-            used = S.x0_predict(pdev, out_scale, A, ds.logk[i].reshape(-1), ds.f[i].reshape(-1),
-                                x[i].reshape(-1), use_fallback=(mode == "cnn"),
-                                workspace=ws[i % nstreams], stream=st)
+            used = S.x0_predict_coarse(pdev, out_scale, factor, sweeps, A,
+                                       ds.logk[i].reshape(-1), ds.f[i].reshape(-1),
+                                       x[i].reshape(-1), use_fallback=(mode == "cnn"),
+                                       workspace=ws[i % nstreams], stream=st)
             if mode == "cnn":
                 fallback[i] = used
 
         blocks, status, secs = solve_all(ds.logk, ds.f, x, nstreams=nstreams, x0_fn=x0_fn,
                                          log=lambda *a: None)
         res[mode] = {"blocks": blocks, "status": status, "seconds": secs}
-        log(f"  eval {mode}: mean blocks {blocks.mean():.1f}, mean time {secs.mean() * 1e3:.1f} ms, "
-            f"not converged {int(np.sum(status != S.OK))}")
+        log(f"  eval {mode} (factor {factor}, sweeps {sweeps}): mean blocks {blocks.mean():.1f}, "
+            f"mean time {secs.mean() * 1e3:.1f} ms, not converged {int(np.sum(status != S.OK))}")
     res["fallback"] = fallback
     return res
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--samples", type=int, default=2048)
+    ap.add_argument("--samples", type=int, default=2560)
     ap.add_argument("--val", type=int, default=128)
     ap.add_argument("--eval", type=int, default=64)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--coarsen", type=int, default=COARSEN)
+    ap.add_argument("--sweeps", type=int, nargs="+", default=[0, 32, 128, 512],
+                    help="Jacobi sweep counts to evaluate; the fastest (with the fallback rule) "
+                         "is stored with the model")
     ap.add_argument("--out", default=DEFAULT_MODEL)
     args = ap.parse_args(argv)
     import torch
@@ -275,22 +304,36 @@ def main(argv=None):
     torch.cuda.init()
     train_ds = generate(args.samples, args.seed, nstreams=args.streams, device=dev)
     val_ds = generate(args.val, args.seed + 1, nstreams=args.streams, device=dev)
-    params, out_scale, hist, train_s, steps = train(train_ds, args.epochs, args.batch, args.lr,
-                                                    val=val_ds)
-    meta = {"grid": GRID, "samples": args.samples, "val": args.val, "epochs": args.epochs,
-            "batch": args.batch, "lr": args.lr, "seed": args.seed, "steps": steps,
-            "train_seconds": train_s, "history": hist,
-            "data_mean_blocks": float(train_ds.blocks.mean()),
-            "data_seconds": float(train_ds.seconds.sum())}
-    save_model(args.out, params, out_scale, meta)
-    _log(f"saved {args.out} (out_scale {out_scale:.4e})")
+    data_mean_blocks = float(train_ds.blocks.mean())
+    data_seconds = float(train_ds.seconds.sum())
+    train_c, val_c = coarsen(train_ds, args.coarsen), coarsen(val_ds, args.coarsen)
     del train_ds
+    params, out_scale, hist, train_s, steps = train(train_c, args.epochs, args.batch, args.lr,
+                                                    val=val_c)
+    del train_c
     ev_ds = generate(args.eval, args.seed + 2, nstreams=args.streams, device=dev)
-    res = evaluate(params, out_scale, ev_ds)
-    summary = {m: {"mean_blocks": float(res[m]["blocks"].mean()),
-                   "mean_ms": float(res[m]["seconds"].mean() * 1e3)}
-               for m in ("zero", "cnn", "cnn_nofallback")}
-    summary["fallback_rate"] = float(res["fallback"].mean())
+    evals = {}
+    zero = None
+    for sw in args.sweeps:
+        res = evaluate(params, out_scale, ev_ds, args.coarsen, sw,
+                       modes=("cnn", "cnn_nofallback") if zero else None)
+        if zero is None:
+            zero = res["zero"]
+        evals[sw] = {m: {"mean_blocks": float(res[m]["blocks"].mean()),
+                         "mean_ms": float(res[m]["seconds"].mean() * 1e3)}
+                     for m in ("cnn", "cnn_nofallback")}
+        evals[sw]["fallback_rate"] = float(res["fallback"].mean())
+    best = min(args.sweeps, key=lambda sw: evals[sw]["cnn"]["mean_ms"])
+    summary = {"zero": {"mean_blocks": float(zero["blocks"].mean()),
+                        "mean_ms": float(zero["seconds"].mean() * 1e3)},
+               "by_sweeps": {str(k): v for k, v in evals.items()}, "chosen_sweeps": best}
+    meta = {"grid": GRID, "coarsen": args.coarsen, "sweeps": best, "samples": args.samples,
+            "val": args.val, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+            "seed": args.seed, "steps": steps, "train_seconds": train_s, "history": hist,
+            "data_mean_blocks": data_mean_blocks, "data_seconds": data_seconds,
+            "eval": summary}
+    save_model(args.out, params, out_scale, meta)
+    _log(f"saved {args.out} (out_scale {out_scale:.4e}, sweeps {best})")
     _log("EVAL " + json.dumps(summary))
 
 

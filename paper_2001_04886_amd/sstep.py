@@ -32,6 +32,7 @@ EXPORTS = (
     "sstep_batch_plan_destroy", "sstep_gmres_solve_batched",
     "sstep_cnn_param_count", "sstep_cnn_workspace_bytes", "sstep_cnn_forward",
     "sstep_cnn_gradient", "sstep_cnn_adam", "sstep_cnn_train_step", "sstep_x0_predict",
+    "sstep_grid_pool", "sstep_x0_coarse_workspace_bytes", "sstep_x0_predict_coarse",
 )
 
 
@@ -118,6 +119,13 @@ def load(path: str | None = None):
     lib.sstep_cnn_train_step.restype = i32
     lib.sstep_x0_predict.argtypes = [vp, dp, sp, vp, vp, vp, i32, C.POINTER(C.c_int), op_]
     lib.sstep_x0_predict.restype = i32
+    lib.sstep_grid_pool.argtypes = [vp, vp, i32, i32, i32, i32, vp]
+    lib.sstep_grid_pool.restype = i32
+    lib.sstep_x0_coarse_workspace_bytes.argtypes = [i32, i32, i32]
+    lib.sstep_x0_coarse_workspace_bytes.restype = C.c_size_t
+    lib.sstep_x0_predict_coarse.argtypes = [vp, dp, i32, i32, sp, vp, vp, vp, i32,
+                                            C.POINTER(C.c_int), op_]
+    lib.sstep_x0_predict_coarse.restype = i32
     _lib = lib
     return lib
 
@@ -448,4 +456,37 @@ def x0_predict(params, out_scale, A: Stencil, logk, f, x0, use_fallback=True, wo
         _f32(params, cnn_param_count(), "params"), float(out_scale), C.byref(sc),
         _f32(logk, A.N, "logk"), _f64(f, A.N, "f"), _f64(x0, A.N, "x0"),
         1 if use_fallback else 0, C.byref(used), C.byref(o)), "x0_predict")
+    return bool(used.value)
+
+
+def grid_pool(x, factor: int, out=None, stream=None):
+    """Block averages over factor x factor cells of x (float64 [B][ny][nx] or
+    [ny][nx]) -> [B][ny/factor][nx/factor] (or 2-D), on the device."""
+    import torch
+    B, ny, nx = _bhw(x)
+    shape = (B, ny // factor, nx // factor) if x.dim() == 3 else (ny // factor, nx // factor)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=x.device)
+    nc = B * (ny // factor) * (nx // factor)
+    _check(load().sstep_grid_pool(_f64(x, B * ny * nx, "x"), _f64(out, nc, "out"), B, nx, ny,
+                                  int(factor), _stream(stream)), "grid_pool")
+    return out
+
+
+def x0_coarse_workspace_bytes(nx: int, ny: int, factor: int) -> int:
+    return int(load().sstep_x0_coarse_workspace_bytes(int(nx), int(ny), int(factor)))
+
+
+def x0_predict_coarse(params, out_scale, factor: int, sweeps: int, A: Stencil, logk, f, x0,
+                      use_fallback=True, workspace=None, stream=None) -> bool:
+    """Fill x0 with the coarse-grid network guess (block-averaged inputs,
+    bilinear interpolation, damped Jacobi sweeps) for A x = f; returns True
+    when the fallback rule replaced it by zero."""
+    sc = A.c_struct()
+    used = C.c_int(0)
+    o = options(workspace=workspace, stream=stream)
+    _check(load().sstep_x0_predict_coarse(
+        _f32(params, cnn_param_count(), "params"), float(out_scale), int(factor), int(sweeps),
+        C.byref(sc), _f32(logk, A.N, "logk"), _f64(f, A.N, "f"), _f64(x0, A.N, "x0"),
+        1 if use_fallback else 0, C.byref(used), C.byref(o)), "x0_predict_coarse")
     return bool(used.value)

@@ -153,3 +153,77 @@ def test_adam_two_steps_closed_form():
     mh = (b1 * g1 + g2) / (1 + b1)
     vh = (b2 * g1 ** 2 + g2 ** 2) / (1 + b2)
     np.testing.assert_allclose(p, p1 - lr * mh / (np.sqrt(vh) + eps), rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# coarse-grid guess: block averages, bilinear interpolation, Jacobi sweeps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("factor", [1, 2, 4, 8])
+def test_pool_is_block_mean(factor):
+    # against numpy's reshape-and-mean of the same blocks
+    B, ny, nx = 2, 8 * 3, 8 * 5
+    x = rnd((B, ny, nx), 11)
+    ref = x.reshape(B, ny // factor, factor, nx // factor, factor).mean(axis=(2, 4))
+    np.testing.assert_allclose(R.pool(x, factor), ref, rtol=1e-14, atol=1e-15)
+    np.testing.assert_array_equal(R.pool(np.full((ny, nx), 2.5), factor), 2.5)
+
+
+@pytest.mark.parametrize("factor", [2, 4, 8])
+def test_upsample_matches_library_bilinear(factor):
+    # torch's bilinear interpolation with half-cell centres (align_corners
+    # False) is the same map, written independently
+    torch = pytest.importorskip("torch")
+    xc = rnd((5, 7), 12)
+    ref = torch.nn.functional.interpolate(torch.tensor(xc)[None, None], scale_factor=factor,
+                                          mode="bilinear", align_corners=False)[0, 0].numpy()
+    np.testing.assert_allclose(R.upsample(xc, factor), ref, rtol=1e-13, atol=1e-14)
+
+
+def test_upsample_reproduces_affine_fields_inside():
+    # at fine points whose two coarse neighbours lie inside the coarse grid the
+    # interpolant of an affine field is the field itself
+    factor, nyc, nxc = 4, 6, 9
+    J, I = np.meshgrid(np.arange(nyc), np.arange(nxc), indexing="ij")
+    xc = 0.3 + 1.7 * I - 0.9 * J
+    x = R.upsample(xc, factor)
+    u = (np.arange(nxc * factor) + 0.5) / factor - 0.5
+    w = (np.arange(nyc * factor) + 0.5) / factor - 0.5
+    inside_x = (u >= 0) & (u <= nxc - 1)
+    inside_y = (w >= 0) & (w <= nyc - 1)
+    ref = 0.3 + 1.7 * u[None, :] - 0.9 * w[:, None]
+    m = inside_y[:, None] & inside_x[None, :]
+    np.testing.assert_allclose(x[m], ref[m], rtol=1e-13, atol=1e-13)
+    # constants everywhere, the edges included
+    np.testing.assert_allclose(R.upsample(np.full((nyc, nxc), -1.25), factor), -1.25, rtol=0, atol=0)
+
+
+def _diffusion_operator(n, seed):
+    import oracle as O
+    from paper_2001_04886_amd import problems as P
+    logk = P.grf(n, 0.2, seed=seed)
+    return O.Operator(2, n, n, coef=P.diffusion_coef(logk)), logk
+
+
+def test_jacobi_sweep_matches_dense_formula():
+    from helpers import dense
+    A, _ = _diffusion_operator(6, 3)
+    M = dense(A)
+    f, x = rnd(36, 13), rnd(36, 14)
+    ref = x + 0.8 * (f - M @ x) / np.diag(M)
+    np.testing.assert_allclose(R.jacobi(A, f, x, 1), ref, rtol=1e-13, atol=1e-13)
+    # the solution is a fixed point
+    xs = np.linalg.solve(M, f)
+    np.testing.assert_allclose(R.jacobi(A, f, xs, 5), xs, rtol=1e-10, atol=1e-12)
+
+
+def test_coarse_guess_with_factor_one_is_the_fine_guess():
+    # factor 1, no sweeps: the composition reduces to predict_x0 (with log k
+    # rounded to float32 as the network input is stored)
+    n = 12
+    A, logk = _diffusion_operator(n, 4)
+    f = rnd((n, n), 15)
+    params = 0.1 * rnd(R.param_count(), 16)
+    ref = R.predict_x0(params, 0.3, logk.astype(np.float32).astype(np.float64)[None], f[None])[0]
+    np.testing.assert_allclose(R.predict_x0_coarse(params, 0.3, 1, 0, A, logk, f), ref.ravel(),
+                               rtol=1e-13, atol=1e-13)

@@ -362,3 +362,93 @@ def test_invalid_arguments_rejected():
                                  None, a.data_ptr(), C.byref(o)) == S.ERR_ARG
     assert lib.sstep_cnn_adam(p.data_ptr(), p.data_ptr(), p.data_ptr(), p.data_ptr(), 0, 1e-3,
                               C.byref(o)) == S.ERR_ARG
+
+
+# ---------------------------------------------------------------------------
+# coarse-grid guess (block averages, network on the coarse grid, bilinear
+# interpolation, damped Jacobi sweeps)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("B,ny,nx,factor", [(1, 8, 8, 1), (3, 40, 48, 4), (2, 256, 256, 8),
+                                            (1, 24, 16, 8)])
+def test_grid_pool_matches_oracle(B, ny, nx, factor):
+    x = np.random.default_rng(B + nx).standard_normal((B, ny, nx))
+    out = S.grid_pool(dev64(x), factor)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.cpu().numpy(), R.pool(x, factor), rtol=1e-14, atol=1e-15)
+
+
+def coarse_guess(params, scale, factor, sweeps, A, logk, f, use_fallback=False):
+    n = A.N
+    x0 = torch.empty(n, dtype=torch.float64, device=DEV)
+    used = S.x0_predict_coarse(dev32(params), scale, factor, sweeps, A, dev32(logk.ravel()),
+                               dev64(f), x0, use_fallback=use_fallback)
+    torch.cuda.synchronize()
+    return x0.cpu().numpy(), used
+
+
+@pytest.mark.parametrize("n,factor", [(48, 4), (64, 8), (40, 1)])
+def test_x0_predict_coarse_passthrough_exact(n, factor):
+    # passthrough network: coarse guess = bf16(f_c / rms f_c) rms f_c * scale
+    # exactly; then only the interpolation, whose FP64 result must agree to
+    # rounding
+    logk, f, coef, A, Aor = diffusion_case(n, 7)
+    x0, used = coarse_guess(passthrough_params(), 0.7, factor, 0, A, logk, f)
+    assert not used
+    fc = R.pool(f.reshape(n, n), factor)
+    rc = R.rms(fc[None])[0]
+    ref = R.upsample(bf16(fc / rc) * rc * 0.7, factor).ravel()
+    np.testing.assert_allclose(x0, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_x0_predict_coarse_jacobi_sweeps():
+    # the sweeps alone, from the GPU's unsmoothed guess, against the oracle's
+    n, factor = 64, 8
+    logk, f, coef, A, Aor = diffusion_case(n, 9)
+    params = he_params(21)
+    x_0, _ = coarse_guess(params, 0.2, factor, 0, A, logk, f)
+    for sweeps in (1, 2, 7):
+        xs, _ = coarse_guess(params, 0.2, factor, sweeps, A, logk, f)
+        ref = R.jacobi(Aor, f, x_0, sweeps)
+        assert rel(xs, ref) <= 1e-12, (sweeps, rel(xs, ref))
+
+
+def test_x0_predict_coarse_matches_oracle():
+    # the whole composition against the FP64 reference at the forward bar
+    # (bf16-stored activations); 64^2 grid on an 8^2 coarse grid, 3 sweeps
+    n, factor = 64, 8
+    logk, f, coef, A, Aor = diffusion_case(n, 11)
+    params = he_params(22)
+    x0, _ = coarse_guess(params, 0.4, factor, 3, A, logk, f)
+    ref = R.predict_x0_coarse(params, 0.4, factor, 3, Aor, logk, f.reshape(n, n))
+    assert rel(x0, ref) <= 1e-2, rel(x0, ref)
+
+
+def test_x0_predict_coarse_fallback_and_arguments():
+    import oracle as O
+    n, factor = 48, 4
+    logk, f, coef, A, Aor = diffusion_case(n, 13)
+    # a hugely scaled passthrough guess: ||f - A x0|| >> ||f|| -> x0 = 0
+    x0, used = coarse_guess(passthrough_params(), 1e6, factor, 0, A, logk, f, use_fallback=True)
+    assert used and np.all(x0 == 0.0)
+    # a zero network: the guess is 0 after interpolation, then the sweeps of
+    # Jacobi from 0; the fallback keeps it when it beats x0 = 0
+    zeros = np.zeros(R.param_count())
+    xz, used = coarse_guess(zeros, 0.5, factor, 50, A, logk, f, use_fallback=True)
+    ref = R.jacobi(Aor, f, np.zeros(n * n), 50)
+    if not used:
+        assert rel(xz, ref) <= 1e-12
+        assert np.linalg.norm(f - O.apply(Aor, xz)) < np.linalg.norm(f)
+    lib = S.load()
+    o = S.options()
+    sc = A.c_struct()
+    p = torch.zeros(R.param_count() + 4, dtype=torch.float32, device=DEV)
+    l32 = torch.zeros(n * n, dtype=torch.float32, device=DEV)
+    a = torch.zeros(n * n, dtype=torch.float64, device=DEV)
+    used_c = C.c_int(0)
+    for factor_, sweeps in ((5, 0), (0, 0), (4, -1)):
+        assert lib.sstep_x0_predict_coarse(p.data_ptr(), 1.0, factor_, sweeps, C.byref(sc),
+                                           l32.data_ptr(), a.data_ptr(), a.data_ptr(), 0,
+                                           C.byref(used_c), C.byref(o)) == S.ERR_ARG
+    assert lib.sstep_x0_coarse_workspace_bytes(n, n, 5) == 0
+    assert lib.sstep_grid_pool(a.data_ptr(), a.data_ptr(), 1, n, n, 5, None) == S.ERR_ARG

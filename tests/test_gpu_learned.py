@@ -26,9 +26,9 @@ def test_committed_model_exists():
 
 def test_trained_guess_gain_on_held_out_problems():
     S.load()
-    params, out_scale, _ = LN.load_model()
+    params, out_scale, meta = LN.load_model()
     ds = LN.generate(4, 7000, nstreams=1)
-    res = LN.evaluate(params, out_scale, ds)
+    res = LN.evaluate(params, out_scale, ds, meta["coarsen"], meta["sweeps"])
     for mode in ("zero", "cnn", "cnn_nofallback"):
         assert np.all(res[mode]["status"] == S.OK), mode
     zero, raw = res["zero"]["blocks"], res["cnn_nofallback"]["blocks"]
