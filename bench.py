@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--nsys", type=int, default=512)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--omin-iters", type=int, default=600)
-    ap.add_argument("--eval-samples", type=int, default=16)
+    ap.add_argument("--eval-samples", type=int, default=64)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

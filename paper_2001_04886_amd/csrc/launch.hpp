@@ -438,7 +438,9 @@ inline void gram_geometry(long long N, int ncx, int nz, int* KZ, int* CA, int* n
     *KZ = gram_kz(nz);
     *CA = gram_ca(*KZ);
     *nct = (ncx + 4 * *CA - 1) / (4 * *CA);
-    long long nch = std::min<long long>((N + 8191) / 8192, std::max(1, 2048 / *nct));
+    // chunks of at least 2048 points (16 steps of the kernel), about 2048
+    // workgroups in all on large grids
+    long long nch = std::min<long long>((N + 2047) / 2048, std::max(1, 2048 / *nct));
     nch = std::max<long long>(1, std::min<long long>(nch, 512));
     long long ck = round_up((N + nch - 1) / nch, 512);
     nch = (N + ck - 1) / ck;
