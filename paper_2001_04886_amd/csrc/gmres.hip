@@ -139,21 +139,28 @@ __global__ __launch_bounds__(kThreads) void k_gm_cycle_start(GmArrays a,
 // Gram of the stored basis against y_1..y_s.  Stored column 0 of block i is
 // nu_i times the normalised w_i, hence the row scaling by 1/nu_i.
 __global__ __launch_bounds__(kThreads) void k_gm_proj(GmArrays a) {
+    // workgroup i: the s columns of T_i, from the factor of W_i staged in LDS
+    // (the triangular solves then run on LDS instead of chains of global loads)
+    __shared__ GramFactor F;
     GmState* st = a.st;
     if (st->done) return;
-    const int s = st->s, kb = st->kb;
-    for (int idx = threadIdx.x; idx < kb * s; idx += kThreads) {
-        const int i = idx / s, l = idx % s + 1;  // block i, Y column l
+    const int s = st->s, kb = st->kb, i = blockIdx.x;
+    if (i >= kb) return;
+    {
+        const double* src = reinterpret_cast<const double*>(&a.Wf[i]);
+        double* dst = reinterpret_cast<double*>(&F);
+        for (int t = threadIdx.x; t < (int)(sizeof(GramFactor) / sizeof(double)); t += kThreads)
+            dst[t] = src[t];
+    }
+    __syncthreads();
+    const double inu = st->inv_nu[i];
+    for (int l = 1 + (int)threadIdx.x; l <= s; l += kThreads) {  // Y column l
         double c[kMaxS];
+        for (int q = 0; q < s; ++q) c[q] = a.Gout[(i * s + q) * s + (l - 1)] * (q == 0 ? inu : 1.0);
+        gram_solve(F, c, c);
         for (int q = 0; q < s; ++q) {
-            const double sc = q == 0 ? st->inv_nu[i] : 1.0;
-            c[q] = a.Gout[(i * s + q) * s + (l - 1)] * sc;
-        }
-        gram_solve(a.Wf[i], c, c);
-        for (int q = 0; q < s; ++q) {
-            const double sc = q == 0 ? st->inv_nu[i] : 1.0;
             a.T[(i * s + q) * (s + 1) + l] = c[q];
-            a.coefM[(i * s + q) * s + (l - 1)] = -c[q] * sc;
+            a.coefM[(i * s + q) * s + (l - 1)] = -c[q] * (q == 0 ? inu : 1.0);
             if (l == 1) a.T[(i * s + q) * (s + 1)] = 0.0;
         }
     }
@@ -181,15 +188,19 @@ __global__ __launch_bounds__(64) void k_gm_block(GmArrays a) {
         gram_factor(W, kMaxS, s, st->rank_tol, &F);
         const int q = F.rank;
         if (q == s) {
-            double h[kMaxS];
+            double h[kMaxS], g[kMaxS];
             for (int p = 0; p < s; ++p) h[p] = a.Gout[p * s1 + s] * (p == 0 ? d0 : 1.0);
-            gram_solve(F, h, st->g);
-            for (int p = 0; p < s; ++p) st->coefN4b[p] = -st->g[p] * (p == 0 ? d0 : 1.0);
+            gram_solve(F, h, g);
+            for (int p = 0; p < s; ++p) {
+                st->g[p] = g[p];
+                st->coefN4b[p] = -g[p] * (p == 0 ? d0 : 1.0);
+            }
             st->skip_n4b = 0;
         } else if (q > 0) {
-            double h[kMaxS];
+            double h[kMaxS], g[kMaxS];
             for (int p = 0; p < q; ++p) h[p] = W[p + q * kMaxS];
-            gram_solve_leading(F, q, h, st->g);
+            gram_solve_leading(F, q, h, g);
+            for (int p = 0; p < s; ++p) st->g[p] = p < q ? g[p] : 0.0;
             st->skip_n4b = 1;
         } else {
             st->err = SSTEP_ERR_NONFINITE;
@@ -232,11 +243,17 @@ __global__ __launch_bounds__(kThreads) void k_gm_nu(GmArrays a, const double* __
 // W_i (D = L^T L).  Workgroup i handles the rows of block i (workgroup kb
 // also the row of w_{k+1}).
 __global__ __launch_bounds__(kThreads) void k_gm_hess_cols(GmArrays a) {
+    // chunk of earlier basis columns staged in LDS: CH rows of T and the
+    // workgroup's rows of Gbar over those columns (loaded by all threads, so
+    // the long sum over earlier columns runs on LDS, not on chains of global loads)
+    constexpr int CH = 128;
     __shared__ double gs[(kMaxS + 1) * kMaxS];
+    __shared__ double Tl[CH * (kMaxS + 1)];
+    __shared__ double Gl[(kMaxS + 1) * CH];
     __shared__ GramFactor F;
     GmState* st = a.st;
     if (st->done) return;
-    const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
+    const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg, s1 = s + 1;
     const int q = a.Wf[kb].rank;
     const int bi = blockIdx.x;                 // row block
     const int r0 = bi * s;
@@ -249,28 +266,49 @@ __global__ __launch_bounds__(kThreads) void k_gm_hess_cols(GmArrays a) {
         for (int i = threadIdx.x; i < (int)(sizeof(GramFactor) / sizeof(double)); i += kThreads)
             dst[i] = src[i];
     }
+    // Z_k B part of each entry (rr, j)
     for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
         const int rr = idx % nr, j = idx / nr, r = r0 + rr;
         double val = 0.0;
         for (int l = 0; l <= q; ++l) {
-            const double bl = Bc[l + j * (s + 1)];
+            const double bl = Bc[l + j * s1];
             if (bl == 0.0) continue;
             double z;
-            if (r < c0) z = a.T[r * (s + 1) + l];
+            if (r < c0) z = a.T[r * s1 + l];
             else if (r < c0 + q) z = (l < q) ? (r - c0 == l ? 1.0 : 0.0) : st->g[r - c0];
             else z = (l == q) ? nu : 0.0;
             val += bl * z;
         }
-        if (r <= c0) {
-            for (int cp = (r > 0 ? r - 1 : 0); cp < c0; ++cp) {
-                const double t = a.T[cp * (s + 1) + j];
-                if (t != 0.0) val -= a.G[r + (long long)cp * ldg] * t;
-            }
-        }
-        a.G[r + (long long)(c0 + j) * ldg] = val;
         gs[rr + j * (kMaxS + 1)] = val;
     }
+    // minus sum over earlier columns cp >= r - 1 of Gbar[r, cp] T[cp, j], rows r <= c0
+    const int rlast = (r0 + nr - 1 < c0) ? r0 + nr - 1 : c0;  // last row taking part
+    const int cstart = r0 > 0 ? r0 - 1 : 0;
+    if (r0 <= c0) {
+        for (int cb = cstart; cb < c0; cb += CH) {
+            const int nc = (c0 - cb < CH) ? c0 - cb : CH;
+            __syncthreads();
+            for (int t = threadIdx.x; t < nc * s1; t += kThreads) Tl[t] = a.T[(long long)cb * s1 + t];
+            for (int t = threadIdx.x; t < nc * nr; t += kThreads) {
+                const int cc = t / nr, rr = t % nr;
+                Gl[rr * CH + cc] = a.G[r0 + rr + (long long)(cb + cc) * ldg];
+            }
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
+                const int rr = idx % nr, j = idx / nr, r = r0 + rr;
+                if (r > rlast) continue;
+                const int lo = (r > 0 ? r - 1 : 0) - cb;
+                double acc = 0.0;
+                for (int cc = lo > 0 ? lo : 0; cc < nc; ++cc) acc += Gl[rr * CH + cc] * Tl[cc * s1 + j];
+                gs[rr + j * (kMaxS + 1)] -= acc;
+            }
+        }
+    }
     __syncthreads();
+    for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
+        const int rr = idx % nr, j = idx / nr;
+        a.G[r0 + rr + (long long)(c0 + j) * ldg] = gs[rr + j * (kMaxS + 1)];
+    }
     // L scaling: rows of block bi (rank qi), plus the unit row of w_{k+1}
     const int qi = (bi < kb) ? s : q;
     for (int idx = threadIdx.x; idx < nr * q; idx += kThreads) {
@@ -289,6 +327,11 @@ __global__ __launch_bounds__(kThreads) void k_gm_hess_cols(GmArrays a) {
 // Givens QR of the new columns of L Gbar and the least-squares residual
 // estimate |rhs[ncols]|; stopping tests of the block.
 __global__ __launch_bounds__(64) void k_gm_givens(GmArrays a) {
+    // rows c0 .. c0+q of the q new columns, their rotations and the rotated
+    // rhs are worked on in LDS (read-modify-write chains through global
+    // memory would wait a memory round trip per step)
+    __shared__ double cw[kMaxS][kMaxS + 2];
+    __shared__ double csl[kMaxS], snl[kMaxS], rh[kMaxS + 1];
     GmState* st = a.st;
     if (st->done) return;
     const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
@@ -302,34 +345,45 @@ __global__ __launch_bounds__(64) void k_gm_givens(GmArrays a) {
             col[i] = cth * x0 + sth * x1;
             x0 = -sth * x0 + cth * x1;
         }
-        col[c0] = x0;
+        cw[threadIdx.x][0] = x0;
+        for (int t = 1; t <= q; ++t) cw[threadIdx.x][t] = col[c0 + t];
     }
+    for (int t = threadIdx.x; t <= q; t += 64) rh[t] = a.rhs[c0 + t];
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int j = 0; j < q; ++j) {
-            double* col = a.R + (long long)(c0 + j) * ldg;
-            for (int i = c0; i < c0 + j; ++i) {
-                const double x0 = col[i], x1 = col[i + 1];
-                col[i] = a.cs[i] * x0 + a.sn[i] * x1;
-                col[i + 1] = -a.sn[i] * x0 + a.cs[i] * x1;
+            double* cj = cw[j];
+            for (int t = 0; t < j; ++t) {
+                const double x0 = cj[t], x1 = cj[t + 1];
+                cj[t] = csl[t] * x0 + snl[t] * x1;
+                cj[t + 1] = -snl[t] * x0 + csl[t] * x1;
             }
-            const int cj = c0 + j;
-            const double x0 = col[cj], x1 = col[cj + 1];
+            const double x0 = cj[j], x1 = cj[j + 1];
             double cth = 1.0, sth = 0.0;
             if (x1 != 0.0) {
                 const double h = hypot(x0, x1);
                 cth = x0 / h;
                 sth = x1 / h;
             }
-            a.cs[cj] = cth;
-            a.sn[cj] = sth;
-            col[cj] = cth * x0 + sth * x1;
-            col[cj + 1] = 0.0;
-            const double g0 = a.rhs[cj];
-            a.rhs[cj + 1] = -sth * g0;
-            a.rhs[cj] = cth * g0;
+            csl[j] = cth;
+            snl[j] = sth;
+            cj[j] = cth * x0 + sth * x1;
+            cj[j + 1] = 0.0;
+            const double g0 = rh[j];
+            rh[j + 1] = -sth * g0;
+            rh[j] = cth * g0;
         }
-        const double est = fabs(a.rhs[c0 + q]);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < q) {
+        double* col = a.R + (long long)(c0 + threadIdx.x) * ldg;
+        for (int t = 0; t <= q; ++t) col[c0 + t] = cw[threadIdx.x][t];
+        a.cs[c0 + threadIdx.x] = csl[threadIdx.x];
+        a.sn[c0 + threadIdx.x] = snl[threadIdx.x];
+    }
+    for (int t = threadIdx.x; t <= q; t += 64) a.rhs[c0 + t] = rh[t];
+    if (threadIdx.x == 0) {
+        const double est = fabs(rh[q]);
         const double nu = st->nu_cur;
         st->est = est;
         st->ncols = c0 + q;
@@ -533,7 +587,7 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
                 launch_gram<T>(c, basis, ld, ncx, Yk + ld, ld, s, (const T*)nullptr, 0, 0, N, gpart,
                                a.Gout, done);
                 c.begin(SSTEP_K_SCALAR, 0.0);
-                hipLaunchKernelGGL(k_gm_proj, dim3(1), dim3(kThreads), 0, c.st, a);
+                hipLaunchKernelGGL(k_gm_proj, dim3(kb), dim3(kThreads), 0, c.st, a);
                 SSTEP_HIP(hipGetLastError());
                 c.end();
                 launch_update<T, T, T, T, false>(c, N, Yk + ld, ld, basis, ld, ncx, nullptr,
