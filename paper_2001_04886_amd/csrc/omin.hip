@@ -94,27 +94,40 @@ __global__ __launch_bounds__(kThreads) void k_om_start(OmArrays a, const double*
 // Scalar1: factor W_i (into ring slot), a_i = W_i^{-1} m_i.
 // Gout: s x (s+1) = AP_i^T [AP_i | r].
 __global__ void k_om_step1(OmArrays a, int slot) {
+    // the factorisation works on LDS copies (read-after-write chains through
+    // global memory would wait a memory round trip per step); the factor is
+    // copied out at the end
+    __shared__ double W[kMaxS * kMaxS];
+    __shared__ GramFactor F;
     OmState* st = a.st;
-    if (st->done || threadIdx.x != 0) return;
+    if (st->done) return;
     const int s = st->s;
-    double W[kMaxS * kMaxS], m[kMaxS];
-    for (int q = 0; q < s; ++q) {
-        for (int p = 0; p < s; ++p) W[p + q * kMaxS] = a.Gout[p * (s + 1) + q];
-        m[q] = a.Gout[q * (s + 1) + s];
+    for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x) {
+        const int p = idx % s, q = idx / s;
+        W[p + q * kMaxS] = a.Gout[p * (s + 1) + q];
     }
-    GramFactor* F = &a.Wf[slot];
-    gram_factor(W, kMaxS, s, st->rank_tol, F);
-    if (F->rank == 0) {
-        st->err = SSTEP_ERR_BREAKDOWN;
-        st->done = 1;
-        return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m[kMaxS];
+        for (int q = 0; q < s; ++q) m[q] = a.Gout[q * (s + 1) + s];
+        gram_factor(W, kMaxS, s, st->rank_tol, &F);
+        if (F.rank == 0) {
+            st->err = SSTEP_ERR_BREAKDOWN;
+            st->done = 1;
+        } else {
+            double al[kMaxS];
+            gram_solve(F, m, al);
+            for (int q = 0; q < s; ++q) {
+                st->coef_x[q] = al[q];
+                st->coef_r[q] = -al[q];
+            }
+        }
     }
-    double al[kMaxS];
-    gram_solve(*F, m, al);
-    for (int q = 0; q < s; ++q) {
-        st->coef_x[q] = al[q];
-        st->coef_r[q] = -al[q];
-    }
+    __syncthreads();
+    const double* src = reinterpret_cast<const double*>(&F);
+    double* dst = reinterpret_cast<double*>(&a.Wf[slot]);
+    for (int i = threadIdx.x; i < (int)(sizeof(GramFactor) / sizeof(double)); i += blockDim.x)
+        dst[i] = src[i];
 }
 
 // After x, r updates: recurrence residual norm, iteration count, stop test.
@@ -144,24 +157,35 @@ __global__ __launch_bounds__(kThreads) void k_om_check(OmArrays a, const double*
 // blocks held in ring slots 0..nfill-1; coefficient rows for the P and AP
 // updates.  Gout: (nfill*s) x (s+1) = AP_ring^T Y.
 __global__ __launch_bounds__(kThreads) void k_om_step2(OmArrays a, int nfill) {
+    // workgroup j: the s columns of B_j from the factor of W_j staged in LDS
+    __shared__ GramFactor F;
     OmState* st = a.st;
     if (st->done) return;
-    const int s = st->s, s1 = s + 1;
+    const int s = st->s, s1 = s + 1, j = blockIdx.x;
     const double* Bc = st->Bc;
-    // rows for Y in the AP update: AR = Y Bbasis
-    for (int idx = threadIdx.x; idx < s1 * s; idx += kThreads) {
-        const int t = idx / s, l = idx % s;
-        a.coefAP[t * s + l] = Bc[t + l * s1];
+    if (j == 0) {
+        // rows for Y in the AP update: AR = Y Bbasis
+        for (int idx = threadIdx.x; idx < s1 * s; idx += kThreads) {
+            const int t = idx / s, l = idx % s;
+            a.coefAP[t * s + l] = Bc[t + l * s1];
+        }
     }
-    for (int idx = threadIdx.x; idx < nfill * s; idx += kThreads) {
-        const int j = idx / s, l = idx % s;  // slot j, column l of B_j
+    if (j >= nfill) return;
+    {
+        const double* src = reinterpret_cast<const double*>(&a.Wf[j]);
+        double* dst = reinterpret_cast<double*>(&F);
+        for (int i = threadIdx.x; i < (int)(sizeof(GramFactor) / sizeof(double)); i += kThreads)
+            dst[i] = src[i];
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < s; l += kThreads) {  // column l of B_j
         double c[kMaxS];
         for (int q = 0; q < s; ++q) {
             double v = 0.0;
             for (int t = 0; t <= s; ++t) v += a.Gout[(j * s + q) * s1 + t] * Bc[t + l * s1];
             c[q] = v;
         }
-        gram_solve(a.Wf[j], c, c);
+        gram_solve(F, c, c);
         for (int q = 0; q < s; ++q) {
             a.coefP[(j * s + q) * s + l] = -c[q];
             a.coefAP[(s1 + j * s + q) * s + l] = -c[q];
@@ -258,6 +282,13 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
         SSTEP_HIP(hipGetLastError());
         c.end();
     };
+    // one workgroup per window slot (at least one)
+    auto scalar_slots = [&](auto kern, int nslots, auto... args) {
+        c.begin(SSTEP_K_SCALAR, 0.0);
+        hipLaunchKernelGGL(kern, dim3(nslots > 0 ? nslots : 1), dim3(kThreads), 0, c.st, a, args...);
+        SSTEP_HIP(hipGetLastError());
+        c.end();
+    };
     c.cur_block = -1;
     // ||f||
     launch_norm2(c, N, f, npart);
@@ -275,7 +306,7 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
     // R_0, AR_0 from the current r (Y[:,0]) into slot 0
     auto start_recurrence = [&]() {
         launch_mpk<double>(c, v, Y, ld, s, opt.basis, P, nullptr, done);
-        scalar(k_om_step2, kThreads, 0);  // coefficient rows of AR
+        scalar_slots(k_om_step2, 0, 0);  // coefficient rows of AR
         launch_update<double, double, double, double, false>(c, N, Y, ld, Pr, ld, 0, nullptr,
                                                              a.coefP, Pr, ld, s, nullptr, done,
                                                              2 * s * vb);
@@ -321,7 +352,7 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
                 launch_mpk<double>(c, v, Y, ld, s, opt.basis, P, nullptr, done);
                 launch_gram<double>(c, APr, ld, nfill * s, Y, ld, s + 1, (const double*)nullptr, 0,
                                     0, N, gpart, a.Gout, done);
-                scalar(k_om_step2, kThreads, nfill);
+                scalar_slots(k_om_step2, nfill, nfill);
                 launch_update<double, double, double, double, false>(
                     c, N, Y, ld, Pr, ld, nfill * s, nullptr, a.coefP, Pr + (long long)nslot * s * ld,
                     ld, s, nullptr, done, (2 * s + nfill * s) * vb);
