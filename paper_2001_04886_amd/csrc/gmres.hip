@@ -35,6 +35,7 @@
 namespace sstep {
 
 constexpr int kMaxBlocks = 2048;
+constexpr int kMaxCols = 2048;  // m * s, checked at the C ABI
 
 struct GmState {
     // parameters
@@ -332,16 +333,22 @@ __global__ __launch_bounds__(64) void k_gm_givens(GmArrays a) {
     // memory would wait a memory round trip per step)
     __shared__ double cw[kMaxS][kMaxS + 2];
     __shared__ double csl[kMaxS], snl[kMaxS], rh[kMaxS + 1];
+    __shared__ double csa[kMaxCols], sna[kMaxCols];  // the earlier rotations
     GmState* st = a.st;
     if (st->done) return;
     const int s = st->s, kb = st->kb, c0 = kb * s, ldg = st->ldg;
     const int q = a.Wf[kb].rank;
+    for (int i = threadIdx.x; i < c0; i += 64) {
+        csa[i] = a.cs[i];
+        sna[i] = a.sn[i];
+    }
+    __syncthreads();
     if ((int)threadIdx.x < q) {  // earlier rotations, one thread per new column
         double* col = a.R + (long long)(c0 + threadIdx.x) * ldg;
         double x0 = col[0];
-#pragma unroll 8
+#pragma unroll 16
         for (int i = 0; i < c0; ++i) {
-            const double cth = a.cs[i], sth = a.sn[i], x1 = col[i + 1];
+            const double cth = csa[i], sth = sna[i], x1 = col[i + 1];
             col[i] = cth * x0 + sth * x1;
             x0 = -sth * x0 + cth * x1;
         }
