@@ -39,7 +39,8 @@ def build() -> str:
 
 class _Stencil(C.Structure):
     _fields_ = [("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
-                ("c", C.c_double * 7), ("coef", C.POINTER(C.c_double))]
+                ("c", C.c_double * 7), ("coef", C.POINTER(C.c_double)),
+                ("ilu", C.POINTER(C.c_double))]
 
 
 class _Result(C.Structure):
@@ -92,6 +93,18 @@ def _load():
     lib.orc_sgmres.restype = C.c_int
     lib.orc_sgmres.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, rp,
                                dp, C.c_int, C.POINTER(_CycleDump)]
+    lib.orc_ilu0_factor.restype = C.c_int
+    lib.orc_ilu0_factor.argtypes = [sp, dp]
+    lib.orc_ilu0_solve.restype = None
+    lib.orc_ilu0_solve.argtypes = [sp, dp, dp, dp]
+    lib.orc_ilu0_mul.restype = None
+    lib.orc_ilu0_mul.argtypes = [sp, dp, dp, dp]
+    lib.orc_somin_ilu0.restype = C.c_int
+    lib.orc_somin_ilu0.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, rp, dp,
+                                   C.c_int]
+    lib.orc_sgmres_ilu0.restype = C.c_int
+    lib.orc_sgmres_ilu0.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, rp, dp,
+                                    C.c_int]
     _lib = lib
     return lib
 
@@ -247,3 +260,72 @@ def sgmres(A, f, x0, s, m, tol, max_blocks=0, basis=MONOMIAL, dump=False, hist_c
         out = out + (dict(V=V[: nc + 1].copy(), G=G.T[: nc + 1, :nc].copy(),
                           D=D.T[: nc + 1, : nc + 1].copy(), ncols=nc, blocks=d.blocks),)
     return out
+
+
+# ---------------------------------------------------------------------------
+# ILU(0) right preconditioning (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def ilu0_factor(A: Operator) -> np.ndarray:
+    """Incomplete LU with A's five-point pattern (Sec. 5), shape (5, N): rows
+    are the slots south, west (unit lower factor L), centre, east, north (U).
+    Raises on a zero pivot or a 3-D operator."""
+    LU = np.empty((5, A.N))
+    st = _load().orc_ilu0_factor(A.ref, _dp(LU))
+    if st != OK:
+        raise ValueError(f"ILU(0) factorisation failed (status {st})")
+    return LU
+
+
+def ilu0_solve(A: Operator, LU: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = (L U)^{-1} r."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.empty(A.N)
+    _load().orc_ilu0_solve(A.ref, _dp(np.ascontiguousarray(LU)), _dp(r), _dp(z))
+    return z
+
+
+def ilu0_mul(A: Operator, LU: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = L U x."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.N)
+    _load().orc_ilu0_mul(A.ref, _dp(np.ascontiguousarray(LU)), _dp(x), _dp(y))
+    return y
+
+
+def apply_precond(A: Operator, LU: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """y = A (L U)^{-1} x, the right-preconditioned operator of Sec. 5."""
+    LU = np.ascontiguousarray(LU)
+    s = _Stencil()
+    C.pointer(s)[0] = A._s
+    s.ilu = _dp(LU)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(A.N)
+    _load().orc_apply(C.byref(s), _dp(x), _dp(y))
+    return y
+
+
+def somin_ilu0(A, f, x0, s, k, tol, max_iters=0, hist_cap=100000):
+    """s-step Orthomin(k) on the ILU(0) right-preconditioned system (Sec. 3
+    and Sec. 5).  Returns (x, Result); residuals are true residuals."""
+    lib = _load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    res = _Result()
+    hist = np.zeros(hist_cap)
+    lib.orc_somin_ilu0(A.ref, _dp(f), _dp(x), s, k, tol, max_iters, C.byref(res), _dp(hist),
+                       hist_cap)
+    return x, _res(res, hist)
+
+
+def sgmres_ilu0(A, f, x0, s, m, tol, max_blocks=0, hist_cap=100000):
+    """s-step GMRES(m) on the ILU(0) right-preconditioned system (Sec. 4 and
+    Sec. 5).  Returns (x, Result); residuals are true residuals."""
+    lib = _load()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    res = _Result()
+    hist = np.zeros(hist_cap)
+    lib.orc_sgmres_ilu0(A.ref, _dp(f), _dp(x), s, m, tol, max_blocks, C.byref(res), _dp(hist),
+                        hist_cap)
+    return x, _res(res, hist)

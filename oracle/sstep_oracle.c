@@ -9,7 +9,8 @@
  *   - GMRES(M) (Sec. 2, Alg. 2.2 with eqs. (2)-(3), modified Gram-Schmidt and
  *     Givens QR for the least-squares problem);
  *   - s-step Orthomin(k) / s-step GCR (Sec. 3, Alg. 3.1);
- *   - s-step GMRES(m) (Sec. 4, Alg. 4.1 and 4.2, eqs. (4)-(8)).
+ *   - s-step GMRES(m) (Sec. 4, Alg. 4.1 and 4.2, eqs. (4)-(8));
+ *   - ILU(0) right preconditioning of both s-step methods (Sec. 5).
  *
  * Readings of the paper used here (each is listed with its justification in
  * the design notes of the repository):
@@ -146,12 +147,20 @@ long long orc_size(const orc_stencil *A)
 }
 
 /* y = A x.  Each row sums its neighbour terms in the fixed order
- * -x, +x, -y, +y, -z, +z and then adds the centre term. */
+ * -x, +x, -y, +y, -z, +z and then adds the centre term.  With ILU(0) factors
+ * attached (A->ilu), y = A (L U)^{-1} x. */
 void orc_apply(const orc_stencil *A, const double *x, double *y)
 {
     const int nx = A->nx, ny = A->ny, nz = A->ndim == 3 ? A->nz : 1;
     const long long N = orc_size(A);
     const long long sx = 1, sy = nx, sz = (long long)nx * ny;
+    double *t = NULL;
+    if (A->ilu) {
+        t = malloc(sizeof(double) * N);
+        if (!t) { for (long long p = 0; p < N; ++p) y[p] = NAN; return; }
+        orc_ilu0_solve(A, A->ilu, x, t);
+        x = t;
+    }
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -169,6 +178,7 @@ void orc_apply(const orc_stencil *A, const double *x, double *y)
                 }
                 y[p] = acc + c[0] * x[p];
             }
+    free(t);
 }
 
 /* Power scaling sigma: the smallest power of two >= max_row sum_q |a_pq|
@@ -176,6 +186,8 @@ void orc_apply(const orc_stencil *A, const double *x, double *y)
  * in floating point. */
 double orc_sigma(const orc_stencil *A)
 {
+    /* the preconditioned operator is close to the identity: no scaling */
+    if (A->ilu) return 1.0;
     const long long N = orc_size(A);
     const int nq = A->ndim == 3 ? 7 : 5;
     double bound = 0.0;
@@ -898,4 +910,172 @@ int orc_sgmres(const orc_stencil *A, const double *f, double *x, int s, int m, d
     set_result(res, status, blocks, cycles, matvecs, beta / nf, est / nf, nh);
     free(r);
     return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ILU(0) right preconditioning (Sec. 5)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Column of slot q of row p, or -1 if it lies outside the grid. */
+static long long ilu_col(const orc_stencil *A, long long p, int q)
+{
+    const int nx = A->nx, ny = A->ny;
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    switch (q) {
+        case 0: return j > 0 ? p - nx : -1;
+        case 1: return i > 0 ? p - 1 : -1;
+        case 2: return p;
+        case 3: return i < nx - 1 ? p + 1 : -1;
+        default: return j < ny - 1 ? p + nx : -1;
+    }
+}
+
+/* Incomplete LU with the sparsity pattern of A (no fill): Gaussian
+ * elimination row by row (i-k-j order), where an update a_pj -= l_pk u_kj is
+ * carried out only if (p, j) is in the pattern and dropped otherwise. */
+int orc_ilu0_factor(const orc_stencil *A, double *LU)
+{
+    if (A->ndim != 2) return ORC_ERR_ARG;
+    const long long N = orc_size(A);
+    /* slot q of LU <- stencil coefficient index: south 3, west 1, centre 0,
+     * east 2, north 4 */
+    static const int from[5] = {3, 1, 0, 2, 4};
+    for (int q = 0; q < 5; ++q)
+        for (long long p = 0; p < N; ++p)
+            LU[q * N + p] = ilu_col(A, p, q) < 0 ? 0.0
+                            : (A->coef ? A->coef[from[q] * N + p] : A->c[from[q]]);
+    for (long long p = 0; p < N; ++p) {
+        /* lower entries in increasing column order: p - nx before p - 1 */
+        for (int qk = 0; qk < 2; ++qk) {
+            const long long k = ilu_col(A, p, qk);
+            if (k < 0) continue;
+            const double ukk = LU[2 * N + k];
+            if (ukk == 0.0 || !isfinite(ukk)) return ORC_ERR_BREAKDOWN;
+            const double lpk = LU[qk * N + p] / ukk;
+            LU[qk * N + p] = lpk;
+            for (int qj = 0; qj < 5; ++qj) {
+                const long long cj = ilu_col(A, p, qj);
+                if (cj <= k) continue;
+                for (int qq = 2; qq < 5; ++qq)  /* U part of row k */
+                    if (ilu_col(A, k, qq) == cj) LU[qj * N + p] -= lpk * LU[qq * N + k];
+            }
+        }
+        if (LU[2 * N + p] == 0.0 || !isfinite(LU[2 * N + p])) return ORC_ERR_BREAKDOWN;
+    }
+    return ORC_OK;
+}
+
+/* z = (L U)^{-1} r: forward substitution with the unit lower factor, then
+ * back substitution with U, in the natural order of the unknowns. */
+void orc_ilu0_solve(const orc_stencil *A, const double *LU, const double *r, double *z)
+{
+    const long long N = orc_size(A);
+    for (long long p = 0; p < N; ++p) {
+        double v = r[p];
+        for (int q = 0; q < 2; ++q) {
+            const long long c = ilu_col(A, p, q);
+            if (c >= 0) v -= LU[q * N + p] * z[c];
+        }
+        z[p] = v;
+    }
+    for (long long p = N - 1; p >= 0; --p) {
+        double v = z[p];
+        for (int q = 3; q < 5; ++q) {
+            const long long c = ilu_col(A, p, q);
+            if (c >= 0) v -= LU[q * N + p] * z[c];
+        }
+        z[p] = v / LU[2 * N + p];
+    }
+}
+
+/* y = L (U x). */
+void orc_ilu0_mul(const orc_stencil *A, const double *LU, const double *x, double *y)
+{
+    const long long N = orc_size(A);
+    double *w = malloc(sizeof(double) * N);
+    if (!w) { for (long long p = 0; p < N; ++p) y[p] = NAN; return; }
+    for (long long p = 0; p < N; ++p) {
+        double v = 0.0;
+        for (int q = 2; q < 5; ++q) {
+            const long long c = ilu_col(A, p, q);
+            if (c >= 0) v += LU[q * N + p] * x[c];
+        }
+        w[p] = v;
+    }
+    for (long long p = 0; p < N; ++p) {
+        double v = w[p];
+        for (int q = 0; q < 2; ++q) {
+            const long long c = ilu_col(A, p, q);
+            if (c >= 0) v += LU[q * N + p] * w[c];
+        }
+        y[p] = v;
+    }
+    free(w);
+}
+
+/* Shared frame of the right-preconditioned solves: factor, u = L U x, run the
+ * method on A (L U)^{-1}, x = (L U)^{-1} u. */
+typedef int (*orc_rp_method)(const orc_stencil *B, const double *f, double *u, void *args,
+                             orc_result *res, double *hist, int hist_cap);
+
+static int orc_right_precond(const orc_stencil *A, const double *f, double *x,
+                             orc_rp_method run, void *args, orc_result *res, double *hist,
+                             int hist_cap)
+{
+    const long long N = orc_size(A);
+    if (A->ndim != 2 || N <= 0) {
+        set_result(res, ORC_ERR_ARG, 0, 0, 0, NAN, NAN, 0);
+        return ORC_ERR_ARG;
+    }
+    double *LU = malloc(sizeof(double) * 5 * N), *u = malloc(sizeof(double) * N);
+    if (!LU || !u) {
+        free(LU); free(u);
+        set_result(res, ORC_ERR_NOMEM, 0, 0, 0, NAN, NAN, 0);
+        return ORC_ERR_NOMEM;
+    }
+    int st = orc_ilu0_factor(A, LU);
+    if (st != ORC_OK) {
+        set_result(res, st, 0, 0, 0, NAN, NAN, 0);
+    } else {
+        orc_ilu0_mul(A, LU, x, u);
+        orc_stencil B = *A;
+        B.ilu = LU;
+        st = run(&B, f, u, args, res, hist, hist_cap);
+        orc_ilu0_solve(A, LU, u, x);
+    }
+    free(LU); free(u);
+    return st;
+}
+
+typedef struct { int s, k, max_iters; double tol; } orc_somin_args;
+typedef struct { int s, m, max_blocks; double tol; } orc_sgmres_args;
+
+static int rp_somin(const orc_stencil *B, const double *f, double *u, void *a_, orc_result *res,
+                    double *hist, int hist_cap)
+{
+    const orc_somin_args *a = a_;
+    return orc_somin(B, f, u, a->s, a->k, a->tol, a->max_iters, ORC_BASIS_MONOMIAL, res, hist,
+                     hist_cap, NULL);
+}
+
+static int rp_sgmres(const orc_stencil *B, const double *f, double *u, void *a_, orc_result *res,
+                     double *hist, int hist_cap)
+{
+    const orc_sgmres_args *a = a_;
+    return orc_sgmres(B, f, u, a->s, a->m, a->tol, a->max_blocks, ORC_BASIS_MONOMIAL, res, hist,
+                      hist_cap, NULL);
+}
+
+int orc_somin_ilu0(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
+                   int max_iters, orc_result *res, double *hist, int hist_cap)
+{
+    orc_somin_args a = {s, k, max_iters, tol};
+    return orc_right_precond(A, f, x, rp_somin, &a, res, hist, hist_cap);
+}
+
+int orc_sgmres_ilu0(const orc_stencil *A, const double *f, double *x, int s, int m, double tol,
+                    int max_blocks, orc_result *res, double *hist, int hist_cap)
+{
+    orc_sgmres_args a = {s, m, max_blocks, tol};
+    return orc_right_precond(A, f, x, rp_sgmres, &a, res, hist, hist_cap);
 }

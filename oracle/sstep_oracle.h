@@ -27,6 +27,9 @@ typedef struct {
     int nx, ny, nz;
     double c[7];
     const double *coef;
+    /* optional ILU(0) factors of this operator (orc_ilu0_factor layout).  If
+     * set, the operator is the right-preconditioned A (L U)^{-1} of Sec. 5. */
+    const double *ilu;
 } orc_stencil;
 
 /* basis of the s-dimensional Krylov block */
@@ -87,6 +90,25 @@ int orc_somin(const orc_stencil *A, const double *f, double *x, int s, int k, do
 int orc_sgmres(const orc_stencil *A, const double *f, double *x, int s, int m, double tol,
                int max_blocks, int basis, orc_result *res, double *hist, int hist_cap,
                orc_cycle_dump *dump);
+
+/* ILU(0) right preconditioning (Sec. 5: [A K] K^{-1} x = f with K the inverse
+ * of the incomplete factors, ILU(0) as the paper's preconditioner).  2-D
+ * five-point operators only.  LU is [5][N]; row p keeps the entries of the
+ * factors in the five columns of A's pattern, slot 0: p - nx, 1: p - 1,
+ * 2: p, 3: p + 1, 4: p + nx (0 where the column lies outside the grid).
+ * Slots 0-1 are L (unit diagonal implied), slots 2-4 are U.
+ * orc_ilu0_factor returns ORC_OK, ORC_ERR_ARG (not 2-D) or ORC_ERR_BREAKDOWN
+ * (a zero pivot). */
+int orc_ilu0_factor(const orc_stencil *A, double *LU);
+void orc_ilu0_solve(const orc_stencil *A, const double *LU, const double *r, double *z);
+void orc_ilu0_mul(const orc_stencil *A, const double *LU, const double *x, double *y);
+/* s-step methods on the right-preconditioned system: u = L U x, the method
+ * runs on A (L U)^{-1} u = f, then x = (L U)^{-1} u.  Monomial basis only
+ * (ORC_ERR_ARG otherwise); residuals reported are true residuals f - A x. */
+int orc_somin_ilu0(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
+                   int max_iters, orc_result *res, double *hist, int hist_cap);
+int orc_sgmres_ilu0(const orc_stencil *A, const double *f, double *x, int s, int m, double tol,
+                    int max_blocks, orc_result *res, double *hist, int hist_cap);
 
 #ifdef __cplusplus
 }
