@@ -65,6 +65,7 @@ typedef struct {
 enum { SSTEP_BASIS_MONOMIAL = 0, SSTEP_BASIS_CHEBYSHEV = 1 };
 enum { SSTEP_FP64 = 0, SSTEP_MIXED = 1 };
 enum { SSTEP_METHOD_OMIN = 0, SSTEP_METHOD_GMRES = 1 };
+enum { SSTEP_PRECOND_NONE = 0, SSTEP_PRECOND_ILU0 = 1 };
 
 typedef struct {
     int32_t max_iters;    /* s-Omin: s-step iterations; s-GMRES: s-blocks over all cycles;
@@ -90,6 +91,12 @@ typedef struct {
     int32_t batch_graph;       /* 1: capture the launch in a hipGraph, replay it       */
     int32_t batch_team;        /* 1, 2, 4 or 8 workgroups solving one large system
                                   together (systems of >= 16384 points per member)   */
+    /* single-system solvers: SSTEP_PRECOND_ILU0 runs the method on the right-
+       preconditioned system A M^{-1} u = f, u = M x, M the ILU(0) factors of A
+       (Sec. 5); 2-D only, nx <= 1024, FP64, monomial basis; sigma 0 means 1.
+       A caller-owned workspace must hold sstep_workspace_bytes() +
+       sstep_precond_workspace_bytes() bytes. */
+    int32_t precond;
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */
@@ -160,6 +167,41 @@ int sstep_gmres_solve(const sstep_stencil *A, const double *f, double *x, int s,
  * precision must be SSTEP_FP64. */
 int sstep_omin_solve(const sstep_stencil *A, const double *f, double *x, int s, int k,
                      double tol, const sstep_options *opt, sstep_info *info);
+
+/* ---------------------------------------------------------------------- */
+/* ILU(0) right preconditioning (Sec. 5)                                   */
+/* ---------------------------------------------------------------------- */
+
+/* The paper solves the right-preconditioned form [A K] K^{-1} x = f with K
+ * the inverse of the ILU(0) factors of A.  For a 2-D five-point matrix in
+ * the natural ordering (x fastest) ILU(0) keeps A's off-diagonal entries and
+ * changes only the pivots:
+ *   M = L U = (D + Lo) D^{-1} (D + Up),
+ *   d_p = a_pp - a_{p,p-nx} a_{p-nx,p} / d_{p-nx} - a_{p,p-1} a_{p-1,p} / d_{p-1},
+ * with Lo / Up the strictly lower / upper parts of A (neighbours outside the
+ * grid dropped).  The triangular sweeps run over anti-diagonals on one wave
+ * of the device (latency bound: about nx + ny steps in sequence).
+ * Requirements for all three calls: A 2-D (ERR_ARG otherwise),
+ * 1 <= nx <= 1024, N * 8 < 2^31; every array a DEVICE array, 8-byte aligned,
+ * caller-owned; the call is asynchronous on `stream` except where noted. */
+
+/* Device workspace (bytes) that precond adds to a solve (0 for
+ * SSTEP_PRECOND_NONE or an unsupported operator). */
+size_t sstep_precond_workspace_bytes(const sstep_stencil *A, int precond);
+
+/* d : DEVICE [2N]; d[0..N) receives the pivots d_p, d[N..2N) their
+ * reciprocals.  Synchronises `stream`; returns SSTEP_ERR_BREAKDOWN if a
+ * pivot is zero or not finite. */
+int sstep_ilu0_factor(const sstep_stencil *A, double *d, void *stream);
+
+/* z = M^{-1} r (forward then backward sweep).  d as written by
+ * sstep_ilu0_factor; r, z : DEVICE [N], z must not alias r or d. */
+int sstep_ilu0_solve(const sstep_stencil *A, const double *d, const double *r, double *z,
+                     void *stream);
+
+/* u = M x.  d as written by sstep_ilu0_factor; x, u : DEVICE [N], distinct. */
+int sstep_ilu0_mul(const sstep_stencil *A, const double *d, const double *x, double *u,
+                   void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched s-step GMRES: many independent systems in one persistent launch */

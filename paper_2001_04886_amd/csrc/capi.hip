@@ -100,6 +100,49 @@ int run_solver(const sstep_options* opt_in, size_t need, sstep_info* info, Solve
     });
 }
 
+bool precond_ok(const sstep_stencil* A, const sstep_options* opt, int prec, int basis) {
+    if (!opt || opt->precond == SSTEP_PRECOND_NONE) return true;
+    return opt->precond == SSTEP_PRECOND_ILU0 && ilu0_supported(*A) && prec == SSTEP_FP64 &&
+           basis == SSTEP_BASIS_MONOMIAL;
+}
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+size_t ilu0_workspace(const sstep_stencil& A) {
+    return 4 * align256((size_t)grid_points(A) * 8) + 256;
+}
+// Right-preconditioned solve (Sec. 5): factor, u = M x, run the method on
+// A M^{-1} u = f with the preconditioner attached to the context, x = M^{-1} u.
+// pw: the preconditioner's part of the workspace (ilu0_workspace bytes).
+template <typename Run>
+int precond_solve(Ctx& c, const sstep_stencil& A, double* x, const sstep_options& o, char* pw,
+                  Run&& run) {
+    const StencilView v = make_view(A);
+    const size_t vb = align256((size_t)v.N * 8);
+    double* d = reinterpret_cast<double*>(pw);
+    double* dinv = reinterpret_cast<double*>(pw + vb);
+    double* u = reinterpret_cast<double*>(pw + 2 * vb);
+    double* t = reinterpret_cast<double*>(pw + 3 * vb);
+    int* bad = reinterpret_cast<int*>(pw + 4 * vb);
+    ilu0_factor_launch(c, v, d, dinv, bad);
+    int hb = 0;
+    SSTEP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    SSTEP_HIP(hipStreamSynchronize(c.st));
+    if (hb) return SSTEP_ERR_BREAKDOWN;
+    ilu0_mul_launch(c, v, d, dinv, x, u);
+    sstep_options o2 = o;
+    if (o2.sigma == 0.0) o2.sigma = 1.0;  // A M^{-1} is close to the identity
+    const Ilu0 P{d, dinv, t};
+    c.pc = &P;
+    int st;
+    try {
+        st = run(u, o2);
+    } catch (...) {
+        c.pc = nullptr;
+        throw;
+    }
+    c.pc = nullptr;
+    ilu0_solve_launch(c, v, dinv, u, x, nullptr);
+    return st;
+}
 }  // namespace
 
 extern "C" {
@@ -144,14 +187,22 @@ int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s,
         s > kMaxS || m < 1 || (long long)m * s > 2048 ||
         !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
         (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
-        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0)))) {
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0))) ||
+        !precond_ok(A, opt, prec, basis)) {
         if (info) std::memset(info, 0, sizeof(*info));
         return set_status(info, SSTEP_ERR_ARG);
     }
-    const size_t need = gmres_workspace_bytes(*A, s, m, prec);
+    const size_t base = gmres_workspace_bytes(*A, s, m, prec);
+    const bool pc = opt && opt->precond == SSTEP_PRECOND_ILU0;
+    const size_t need = base + (pc ? ilu0_workspace(*A) : 0);
     const sstep_stencil Acopy = *A;
     return run_solver(opt, need, info, [&](Ctx& c, const sstep_options& o, void* ws, size_t wsb) {
-        return gmres_solve_impl(c, Acopy, f, x, s, m, tol, o, info, ws, wsb);
+        if (!pc) return gmres_solve_impl(c, Acopy, f, x, s, m, tol, o, info, ws, wsb);
+        return precond_solve(c, Acopy, x, o, (char*)ws + base,
+                             [&](double* u, const sstep_options& o2) {
+                                 return gmres_solve_impl(c, Acopy, f, u, s, m, tol, o2, info, ws,
+                                                         base);
+                             });
     });
 }
 
@@ -162,14 +213,74 @@ int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, 
     if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
         s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
         prec != SSTEP_FP64 || (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
-        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0)))) {
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0))) ||
+        !precond_ok(A, opt, prec, basis)) {
         if (info) std::memset(info, 0, sizeof(*info));
         return set_status(info, SSTEP_ERR_ARG);
     }
-    const size_t need = omin_workspace_bytes(*A, s, k);
+    const size_t base = omin_workspace_bytes(*A, s, k);
+    const bool pc = opt && opt->precond == SSTEP_PRECOND_ILU0;
+    const size_t need = base + (pc ? ilu0_workspace(*A) : 0);
     const sstep_stencil Acopy = *A;
     return run_solver(opt, need, info, [&](Ctx& c, const sstep_options& o, void* ws, size_t wsb) {
-        return omin_solve_impl(c, Acopy, f, x, s, k, tol, o, info, ws, wsb);
+        if (!pc) return omin_solve_impl(c, Acopy, f, x, s, k, tol, o, info, ws, wsb);
+        return precond_solve(c, Acopy, x, o, (char*)ws + base,
+                             [&](double* u, const sstep_options& o2) {
+                                 return omin_solve_impl(c, Acopy, f, u, s, k, tol, o2, info, ws,
+                                                        base);
+                             });
+    });
+}
+
+size_t sstep_precond_workspace_bytes(const sstep_stencil* A, int precond) {
+    if (precond != SSTEP_PRECOND_ILU0 || !stencil_ok(A) || !ilu0_supported(*A)) return 0;
+    return ilu0_workspace(*A);
+}
+
+int sstep_ilu0_factor(const sstep_stencil* A, double* d, void* stream) {
+    if (!stencil_ok(A) || !ilu0_supported(*A) || !d || ((uintptr_t)d & 7u)) return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        const StencilView v = make_view(*A);
+        int* bad = nullptr;
+        SSTEP_HIP(hipMallocAsync((void**)&bad, sizeof(int), c.st));
+        ilu0_factor_launch(c, v, d, d + v.N, bad);
+        int hb = 0;
+        SSTEP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, c.st));
+        SSTEP_HIP(hipFreeAsync(bad, c.st));
+        SSTEP_HIP(hipStreamSynchronize(c.st));
+        return hb ? SSTEP_ERR_BREAKDOWN : SSTEP_OK;
+    });
+}
+
+int sstep_ilu0_solve(const sstep_stencil* A, const double* d, const double* r, double* z,
+                     void* stream) {
+    if (!stencil_ok(A) || !ilu0_supported(*A) || !d || !r || !z || z == r ||
+        ((uintptr_t)d & 7u) || ((uintptr_t)r & 7u) || ((uintptr_t)z & 7u))
+        return SSTEP_ERR_ARG;
+    const long long N = grid_points(*A);
+    if ((z < d + 2 * N && d < z + N)) return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        const StencilView v = make_view(*A);
+        ilu0_solve_launch(c, v, d + v.N, r, z, nullptr);
+        return SSTEP_OK;
+    });
+}
+
+int sstep_ilu0_mul(const sstep_stencil* A, const double* d, const double* x, double* u,
+                   void* stream) {
+    if (!stencil_ok(A) || !ilu0_supported(*A) || !d || !x || !u || u == x ||
+        ((uintptr_t)d & 7u) || ((uintptr_t)x & 7u) || ((uintptr_t)u & 7u))
+        return SSTEP_ERR_ARG;
+    return guarded(nullptr, [&]() -> int {
+        Ctx c;
+        c.st = (hipStream_t)stream;
+        const StencilView v = make_view(*A);
+        ilu0_mul_launch(c, v, d, d + v.N, x, u);
+        return SSTEP_OK;
     });
 }
 

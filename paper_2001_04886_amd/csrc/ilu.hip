@@ -1,0 +1,404 @@
+// ilu.hip -- ILU(0) right preconditioning (Sec. 5) of a 2-D five-point
+// stencil: factorisation, preconditioner solve and product.
+//
+// For a five-point matrix in the natural ordering the only fill that
+// elimination creates lies at columns p -+ (nx - 1) and ILU(0) drops it, so
+// the factors keep A's off-diagonal entries and only the pivots change:
+//   M = (D + Lo) D^{-1} (D + Up),
+//   d_p = a_pp - a_{p,p-nx} a_{p-nx,p} / d_{p-nx} - a_{p,p-1} a_{p-1,p} / d_{p-1},
+// Lo / Up the strictly lower (south, west) / upper (east, north) parts of A.
+// (L = I + Lo D^{-1} and U = D + Up are the unit-lower / upper ILU(0)
+// factors.)
+//
+// Point (i, j) of a forward sweep depends on (i-1, j) and (i, j-1), so the
+// sweep runs over the anti-diagonals i + j (the hyperplane order that makes
+// the preconditioner vectorise).  One wave of 64 lanes: lane l owns the CPL
+// columns [l CPL, (l+1) CPL) and reaches row j at step j + l, one step after
+// its west neighbour lane; the west value moves between lanes with a
+// whole-wave DPP shift (no LDS, no barrier), the south value stays in the
+// lane's registers.  The backward sweep mirrors this from the north-east
+// corner.  Loads for step t + D are issued at step t (register ring), every
+// load and store is a raw buffer access whose out-of-grid lanes read 0 /
+// write nothing, so the sweep has no branches and no wait for loads that are
+// still in flight.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/sstep.h"
+#include "kernels.hpp"
+#include "launch.hpp"
+#include "mpk.hpp"
+
+namespace sstep {
+
+namespace {
+
+constexpr int kIluLanes = 64;
+
+// Value of the same register in lane l - 1 (lane 0: 0) / lane l + 1 (lane 63: 0).
+__device__ __forceinline__ double from_lane_below(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, 0x138, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), 0x138, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double from_lane_above(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, 0x130, 0xf, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Buffer resource over coefficient plane q of a variable-coefficient stencil
+// (or an empty one: every access out of range).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t coef_rsrc(const StencilView& A, int q) {
+    return A.coef ? mpk_rsrc(A.coef + (long long)q * A.N, (unsigned)(A.N * 8))
+                  : mpk_rsrc(A.coef, 0u);
+}
+
+// Byte offset of (i, j) or kMpkOff when ok is false.
+__device__ __forceinline__ unsigned ofs(bool ok, int i, int j, int nx) {
+    return ok ? (unsigned)((j * nx + i) * 8) : kMpkOff;
+}
+
+// Number of lanes that own at least one column.
+__host__ __device__ __forceinline__ int ilu_lanes(int nx, int cpl) { return (nx + cpl - 1) / cpl; }
+
+// ---------------------------------------------------------------------------
+// Pivots: d[p] and dinv[p] = 1 / d[p]; *bad = 1 if a pivot is zero or not
+// finite, else 0 (always written).
+// ---------------------------------------------------------------------------
+template <int CPL, int D, bool VC>
+__global__ __launch_bounds__(kIluLanes) void k_ilu0_factor(StencilView A, double* __restrict__ d,
+                                                           double* __restrict__ dinv,
+                                                           int* __restrict__ bad) {
+    const int nx = A.nx, ny = A.ny, lane = threadIdx.x, i0 = lane * CPL;
+    const int nl = ilu_lanes(nx, CPL), T = ny + nl - 1;
+    const __amdgpu_buffer_rsrc_t rc0 = coef_rsrc(A, 0), rw = coef_rsrc(A, 1), re = coef_rsrc(A, 2),
+                                 rs = coef_rsrc(A, 3), rn = coef_rsrc(A, 4);
+    const __amdgpu_buffer_rsrc_t rd = mpk_rsrc(d, (unsigned)(A.N * 8)),
+                                 ri = mpk_rsrc(dinv, (unsigned)(A.N * 8));
+    // per point of a step: centre, (west coef) x (east coef of the west
+    // point), (south coef) x (north coef of the south point)
+    double cc[D][CPL], kw[D][CPL], ks[D][CPL];
+    auto fetch = [&](int t, double (&c0)[CPL], double (&w)[CPL], double (&s)[CPL]) {
+        const int j = t - lane;
+        const bool row = j >= 0 && j < ny;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int i = i0 + c;
+            const bool in = row && i < nx;
+            if constexpr (VC) {
+                c0[c] = mpk_ld<double>(rc0, ofs(in, i, j, nx));
+                w[c] = mpk_ld<double>(rw, ofs(in && i > 0, i, j, nx)) *
+                       mpk_ld<double>(re, ofs(in && i > 0, i - 1, j, nx));
+                s[c] = mpk_ld<double>(rs, ofs(in && j > 0, i, j, nx)) *
+                       mpk_ld<double>(rn, ofs(in && j > 0, i, j - 1, nx));
+            } else {
+                c0[c] = in ? A.c[0] : 1.0;
+                w[c] = (in && i > 0) ? A.c[1] * A.c[2] : 0.0;
+                s[c] = (in && j > 0) ? A.c[3] * A.c[4] : 0.0;
+            }
+        }
+    };
+    // the loop starts D steps early on zeros (rows < 0: nothing stored), so
+    // no load is in flight when it is entered and every entry to its head
+    // sees the same loads outstanding
+#pragma unroll
+    for (int u = 0; u < D; ++u)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cc[u][c] = kw[u][c] = ks[u][c] = 0.0;
+    double south[CPL];  // 1 / d of the point below each owned column
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) south[c] = 0.0;
+    double last = 0.0;  // 1 / d of this lane's last column, previous step
+    bool fail = false;
+    for (int t0 = -D; t0 < T; t0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int t = t0 + u;
+            const int j = t - lane;
+            const bool row = j >= 0 && j < ny;
+            double west = from_lane_below(last);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int i = i0 + c;
+                const bool in = row && i < nx;
+                const double piv = cc[u][c] - ks[u][c] * south[c] - kw[u][c] * west;
+                const double r = 1.0 / piv;
+                fail |= in && !(std::isfinite(piv) && piv != 0.0 && std::isfinite(r));
+                const double rv = in ? r : 0.0;
+                mpk_st<double>(piv, rd, ofs(in, i, j, nx));
+                mpk_st<double>(rv, ri, ofs(in, i, j, nx));
+                south[c] = rv;
+                west = rv;
+            }
+            last = west;
+            fetch(t + D, cc[u], kw[u], ks[u]);
+        }
+    }
+    const bool any = __any(fail);
+    if (lane == 0) *bad = any ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// z = M^{-1} r.  Forward: (D + Lo) w = r, w written to z; backward:
+// (D + Up) z = D w, i.e. z_p = w_p - (a_e z_{p+1} + a_n z_{p+nx}) / d_p, in
+// place.  Each lane reads back only the points it wrote itself.
+// ---------------------------------------------------------------------------
+template <int CPL, int D, bool VC>
+__global__ __launch_bounds__(kIluLanes) void k_ilu0_solve(StencilView A,
+                                                          const double* __restrict__ dinv,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ z,
+                                                          const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int nx = A.nx, ny = A.ny, lane = threadIdx.x, i0 = lane * CPL;
+    const int nl = ilu_lanes(nx, CPL), T = ny + nl - 1;
+    const unsigned nb = (unsigned)(A.N * 8);
+    const __amdgpu_buffer_rsrc_t rw = coef_rsrc(A, 1), re = coef_rsrc(A, 2), rs = coef_rsrc(A, 3),
+                                 rn = coef_rsrc(A, 4);
+    const __amdgpu_buffer_rsrc_t ri = mpk_rsrc(dinv, nb), rr = mpk_rsrc(r, nb), rz = mpk_rsrc(z, nb);
+
+    double v[D][CPL], dv[D][CPL], a1[D][CPL], a2[D][CPL];
+    // forward step t: row j = t - lane
+    auto fetch_f = [&](int t, int u) {
+        const int j = t - lane;
+        const bool row = j >= 0 && j < ny;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int i = i0 + c;
+            const bool in = row && i < nx;
+            v[u][c] = mpk_ld<double>(rr, ofs(in, i, j, nx));
+            dv[u][c] = mpk_ld<double>(ri, ofs(in, i, j, nx));
+            if constexpr (VC) {
+                a1[u][c] = mpk_ld<double>(rw, ofs(in && i > 0, i, j, nx));
+                a2[u][c] = mpk_ld<double>(rs, ofs(in && j > 0, i, j, nx));
+            } else {
+                a1[u][c] = (in && i > 0) ? A.c[1] : 0.0;
+                a2[u][c] = (in && j > 0) ? A.c[3] : 0.0;
+            }
+        }
+    };
+    // backward step t: lane l (counted from the top, m = nl - 1 - l) reaches
+    // row j = ny - 1 - (t - m)
+    const int m = nl - 1 - lane;
+    auto fetch_b = [&](int t, int u) {
+        const int j = ny - 1 - (t - m);
+        const bool row = m >= 0 && j >= 0 && j < ny;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int i = i0 + c;
+            const bool in = row && i < nx;
+            v[u][c] = mpk_ld<double>(rz, ofs(in, i, j, nx));
+            dv[u][c] = mpk_ld<double>(ri, ofs(in, i, j, nx));
+            if constexpr (VC) {
+                a1[u][c] = mpk_ld<double>(re, ofs(in && i < nx - 1, i, j, nx));
+                a2[u][c] = mpk_ld<double>(rn, ofs(in && j < ny - 1, i, j, nx));
+            } else {
+                a1[u][c] = (in && i < nx - 1) ? A.c[2] : 0.0;
+                a2[u][c] = (in && j < ny - 1) ? A.c[4] : 0.0;
+            }
+        }
+    };
+
+    // forward sweep
+    // each sweep starts D steps early on zeros (nothing stored, nothing in
+    // flight at the loop's entry; see k_ilu0_factor)
+    auto clear = [&]() {
+#pragma unroll
+        for (int u = 0; u < D; ++u)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) v[u][c] = dv[u][c] = a1[u][c] = a2[u][c] = 0.0;
+    };
+    clear();
+    double nb_row[CPL];  // value of the previous row in each owned column
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) nb_row[c] = 0.0;
+    double edge = 0.0;
+    for (int t0 = -D; t0 < T; t0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int t = t0 + u;
+            const int j = t - lane;
+            const bool row = j >= 0 && j < ny;
+            double w = from_lane_below(edge);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int i = i0 + c;
+                w = (v[u][c] - a2[u][c] * nb_row[c] - a1[u][c] * w) * dv[u][c];
+                mpk_st<double>(w, rz, ofs(row && i < nx, i, j, nx));
+                nb_row[c] = w;
+            }
+            edge = w;
+            fetch_f(t + D, u);
+        }
+    }
+    // the backward sweep reads the forward result of the lane's own points;
+    // the wait also drains the forward sweep's last (out-of-range) loads
+    __threadfence_block();
+
+    // backward sweep, columns of a lane from the last to the first
+    clear();
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) nb_row[c] = 0.0;
+    edge = 0.0;
+    for (int t0 = -D; t0 < T; t0 += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int t = t0 + u;
+            const int j = ny - 1 - (t - m);
+            const bool row = m >= 0 && j >= 0 && j < ny;
+            double e = from_lane_above(edge);
+#pragma unroll
+            for (int c = CPL - 1; c >= 0; --c) {
+                const int i = i0 + c;
+                e = v[u][c] - dv[u][c] * (a1[u][c] * e + a2[u][c] * nb_row[c]);
+                mpk_st<double>(e, rz, ofs(row && i < nx, i, j, nx));
+                nb_row[c] = e;
+            }
+            edge = e;
+            fetch_b(t + D, u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// u = M x = (D + Lo) D^{-1} (D + Up) x, one thread per point:
+//   y_q = d_q x_q + a_e(q) x_{q+1} + a_n(q) x_{q+nx}     (q = p, p-1, p-nx)
+//   u_p = y_p + a_w(p) y_{p-1} / d_{p-1} + a_s(p) y_{p-nx} / d_{p-nx}
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_ilu0_mul(StencilView A, const double* __restrict__ d,
+                                                       const double* __restrict__ dinv,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ u) {
+    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= A.N) return;
+    const int nx = A.nx, ny = A.ny;
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    auto cf = [&](int q, long long pt) { return A.coef ? A.coef[q * A.N + pt] : A.c[q]; };
+    auto y = [&](long long q, int iq, int jq) {
+        double v = d[q] * x[q];
+        if (iq < nx - 1) v += cf(2, q) * x[q + 1];
+        if (jq < ny - 1) v += cf(4, q) * x[q + nx];
+        return v;
+    };
+    double r = y(p, i, j);
+    if (j > 0) r += cf(3, p) * dinv[p - nx] * y(p - nx, i, j - 1);
+    if (i > 0) r += cf(1, p) * dinv[p - 1] * y(p - 1, i - 1, j);
+    u[p] = r;
+}
+
+// ---------------------------------------------------------------------------
+// One level of matrix powers of the right-preconditioned operator:
+//   out = alpha * si * A(t) + beta * si * in + gam * sp * prev,  t = M^{-1} in
+// (si, sp: optional device scales of in / prev, nullptr = 1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_ilu0_level(
+    StencilView A, const double* __restrict__ in, const double* __restrict__ in_scale,
+    const double* __restrict__ prev, const double* __restrict__ prev_scale, double alpha,
+    double beta, double gam, const double* __restrict__ t, double* __restrict__ out,
+    const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= A.N) return;
+    const int nx = A.nx, ny = A.ny;
+    const int i = (int)(p % nx), j = (int)(p / nx);
+    auto cf = [&](int q) { return A.coef ? A.coef[q * A.N + p] : A.c[q]; };
+    double acc = 0.0;
+    if (i > 0) acc += cf(1) * t[p - 1];
+    if (i < nx - 1) acc += cf(2) * t[p + 1];
+    if (j > 0) acc += cf(3) * t[p - nx];
+    if (j < ny - 1) acc += cf(4) * t[p + nx];
+    acc += cf(0) * t[p];
+    const double si = in_scale ? *in_scale : 1.0;
+    double r = alpha * si * acc;
+    if (beta != 0.0) r += beta * si * in[p];
+    if (gam != 0.0) r += gam * (prev_scale ? *prev_scale : 1.0) * prev[p];
+    out[p] = r;
+}
+
+// columns per lane for a row of nx points (nx <= 64 * 16)
+int ilu_cpl(int nx) {
+    if (nx <= 64) return 1;
+    if (nx <= 128) return 2;
+    if (nx <= 256) return 4;
+    if (nx <= 512) return 8;
+    return 16;
+}
+
+}  // namespace
+
+bool ilu0_supported(const sstep_stencil& A) {
+    return A.ndim == 2 && A.nx >= 1 && A.ny >= 1 && A.nx <= kIluMaxNx &&
+           (long long)A.nx * A.ny * 8 < (1LL << 31);
+}
+
+// Prefetch depth D (steps) per columns-per-lane and coefficient kind: the
+// memory operations of D steps (loads and stores, about 5 per point with
+// coefficient fields, 3 without) must fit the 63 the wait counter tracks.
+#define SSTEP_ILU_CASES(X) X(1, 8, 8) X(2, 4, 8) X(4, 2, 4) X(8, 1, 2) X(16, 1, 1)
+
+void ilu0_factor_launch(Ctx& c, const StencilView& v, double* d, double* dinv, int* bad) {
+    c.begin(SSTEP_K_MPK, (double)v.N * 8.0 * (v.coef ? 7.0 : 2.0));
+    switch (ilu_cpl(v.nx)) {
+#define SSTEP_F(C, DV, DC)                                                                        \
+    case C:                                                                                       \
+        if (v.coef)                                                                               \
+            hipLaunchKernelGGL((k_ilu0_factor<C, DV, true>), dim3(1), dim3(kIluLanes), 0, c.st, v, \
+                               d, dinv, bad);                                                     \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_ilu0_factor<C, DC, false>), dim3(1), dim3(kIluLanes), 0, c.st,  \
+                               v, d, dinv, bad);                                                  \
+        break;
+        SSTEP_ILU_CASES(SSTEP_F)
+#undef SSTEP_F
+    }
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* dinv, const double* r,
+                       double* z, const int* skip) {
+    // algorithmic bytes: r, 1/d (twice), the four neighbour coefficients, the
+    // intermediate written and read, z written
+    c.begin(SSTEP_K_MPK, (double)v.N * 8.0 * (v.coef ? 10.0 : 6.0));
+    switch (ilu_cpl(v.nx)) {
+#define SSTEP_S(C, DV, DC)                                                                         \
+    case C:                                                                                        \
+        if (v.coef)                                                                                \
+            hipLaunchKernelGGL((k_ilu0_solve<C, DV, true>), dim3(1), dim3(kIluLanes), 0, c.st, v,  \
+                               dinv, r, z, skip);                                                  \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_ilu0_solve<C, DC, false>), dim3(1), dim3(kIluLanes), 0, c.st, v, \
+                               dinv, r, z, skip);                                                  \
+        break;
+        SSTEP_ILU_CASES(SSTEP_S)
+#undef SSTEP_S
+    }
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+void ilu0_mul_launch(Ctx& c, const StencilView& v, const double* d, const double* dinv,
+                     const double* x, double* u) {
+    c.begin(SSTEP_K_MPK, (double)v.N * 8.0 * (v.coef ? 7.0 : 4.0));
+    hipLaunchKernelGGL(k_ilu0_mul, dim3((unsigned)((v.N + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c.st, v, d, dinv, x, u);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+void ilu0_level_launch(Ctx& c, const StencilView& v, const double* in, const double* in_scale,
+                       const double* prev, const double* prev_scale, double alpha, double beta,
+                       double gam, const double* t, double* out, const int* skip, double bytes) {
+    c.begin(SSTEP_K_MPK, bytes);
+    hipLaunchKernelGGL(k_ilu0_level, dim3((unsigned)((v.N + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c.st, v, in, in_scale, prev, prev_scale, alpha, beta,
+                       gam, t, out, skip);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+}  // namespace sstep

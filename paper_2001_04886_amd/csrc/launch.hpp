@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sstep.h"
@@ -61,6 +62,15 @@ struct LaunchRec {
     int ev;
 };
 
+// ILU(0) right preconditioner of a 2-D five-point operator (Sec. 5): pivots,
+// their reciprocals, and a scratch vector for M^{-1} of one vector.
+struct Ilu0 {
+    const double* d;
+    const double* dinv;
+    double* t;
+};
+constexpr int kIluMaxNx = 1024;
+
 struct Ctx {
     hipStream_t st = nullptr;
     bool profile = false;
@@ -68,6 +78,9 @@ struct Ctx {
     int nev = 0;
     std::vector<LaunchRec> recs;
     int cur_block = -1;
+    // set while a solve runs on the right-preconditioned operator A M^{-1}:
+    // matrix powers and residuals apply M^{-1} first (FP64 only)
+    const Ilu0* pc = nullptr;
     // totals
     long long launches[SSTEP_K_NCLASS] = {0};
     double ms[SSTEP_K_NCLASS] = {0};
@@ -349,6 +362,17 @@ inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, do
     }
 }
 
+// ILU(0) kernels (ilu.hip).
+bool ilu0_supported(const sstep_stencil& A);
+void ilu0_factor_launch(Ctx& c, const StencilView& v, double* d, double* dinv, int* bad);
+void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* dinv, const double* r,
+                       double* z, const int* skip);
+void ilu0_mul_launch(Ctx& c, const StencilView& v, const double* d, const double* dinv,
+                     const double* x, double* u);
+void ilu0_level_launch(Ctx& c, const StencilView& v, const double* in, const double* in_scale,
+                       const double* prev, const double* prev_scale, double alpha, double beta,
+                       double gam, const double* t, double* out, const int* skip, double bytes);
+
 // Matrix powers of column 0 of Y into columns 1..s: fused launches of at
 // most kMpkMaxL levels each.  Column 0 is read with in_scale applied.  Grids
 // too small to give a fused launch 512 workgroups (a few hundred rows) run one
@@ -360,6 +384,23 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
                        const OpParams& P, const double* in_scale, const int* skip,
                        bool fused_only = false) {
     const double vb = (double)v.N * sizeof(T);
+    if constexpr (std::is_same<T, double>::value) {
+        if (c.pc) {
+            // right-preconditioned operator: per level t = M^{-1} y_{lev-1},
+            // then the level's stencil on t
+            for (int lev = 1; lev <= s; ++lev) {
+                double a, b, g;
+                mpk_level_coefs(lev, basis, P, &a, &b, &g);
+                const double* in = Y + (long long)(lev - 1) * ldy;
+                const double* prev = lev >= 2 ? Y + (long long)(lev - 2) * ldy : nullptr;
+                ilu0_solve_launch(c, v, c.pc->dinv, in, c.pc->t, skip);
+                ilu0_level_launch(c, v, in, lev == 1 ? in_scale : nullptr, prev,
+                                  lev == 2 ? in_scale : nullptr, a, b, g, c.pc->t,
+                                  Y + (long long)lev * ldy, skip, vb * (lev == 1 ? 2.0 : 1.0));
+            }
+            return;
+        }
+    }
     const int L0 = v.ndim == 3 ? std::min(s, 2) : (s >= 8 ? 8 : (s >= 6 ? 6 : (s >= 4 ? 4 : s)));
     if ((!fused_only && mpk_small_grid(v, L0)) || !mpk_fused_fits(v)) {
         for (int lev = 1; lev <= s; ++lev) {
@@ -415,6 +456,10 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
 template <typename TR>
 inline void launch_residual(Ctx& c, const StencilView& v, const double* f, const double* x, TR* r,
                             double* part) {
+    if (c.pc) {  // x is the preconditioned unknown u: the residual is f - A M^{-1} u
+        ilu0_solve_launch(c, v, c.pc->dinv, x, c.pc->t, nullptr);
+        x = c.pc->t;
+    }
     c.begin(SSTEP_K_RESID, (double)v.N * (16.0 + sizeof(TR)));
     const int nseg = stencil_segments(v);
     hipLaunchKernelGGL(k_residual<TR>, dim3((unsigned)stencil_blocks(v)), dim3(kThreads), 0, c.st,

@@ -20,6 +20,7 @@ OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = 0
 MONOMIAL, CHEBYSHEV = 0, 1
 FP64, MIXED = 0, 1
 METHOD_OMIN, METHOD_GMRES = 0, 1
+PRECOND_NONE, PRECOND_ILU0 = 0, 1
 K_MPK, K_GRAM, K_UPDATE, K_RESID, K_SCALAR, K_VEC, K_NCLASS = 0, 1, 2, 3, 4, 5, 6
 KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar", "vec")
 
@@ -33,6 +34,7 @@ EXPORTS = (
     "sstep_cnn_param_count", "sstep_cnn_workspace_bytes", "sstep_cnn_forward",
     "sstep_cnn_gradient", "sstep_cnn_adam", "sstep_cnn_train_step", "sstep_x0_predict",
     "sstep_grid_pool", "sstep_x0_coarse_workspace_bytes", "sstep_x0_predict_coarse",
+    "sstep_precond_workspace_bytes", "sstep_ilu0_factor", "sstep_ilu0_solve", "sstep_ilu0_mul",
 )
 
 
@@ -47,7 +49,7 @@ class OptionsC(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("batch_threads", C.c_int32),
                 ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
-                ("batch_team", C.c_int32)]
+                ("batch_team", C.c_int32), ("precond", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -126,6 +128,14 @@ def load(path: str | None = None):
     lib.sstep_x0_predict_coarse.argtypes = [vp, dp, i32, i32, sp, vp, vp, vp, i32,
                                             C.POINTER(C.c_int), op_]
     lib.sstep_x0_predict_coarse.restype = i32
+    lib.sstep_precond_workspace_bytes.argtypes = [sp, i32]
+    lib.sstep_precond_workspace_bytes.restype = C.c_size_t
+    lib.sstep_ilu0_factor.argtypes = [sp, vp, vp]
+    lib.sstep_ilu0_factor.restype = i32
+    lib.sstep_ilu0_solve.argtypes = [sp, vp, vp, vp, vp]
+    lib.sstep_ilu0_solve.restype = i32
+    lib.sstep_ilu0_mul.argtypes = [sp, vp, vp, vp, vp]
+    lib.sstep_ilu0_mul.restype = i32
     _lib = lib
     return lib
 
@@ -224,7 +234,7 @@ def _stream(stream=None) -> int:
 
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
             workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
-            batch_graph=False, batch_team=0) -> OptionsC:
+            batch_graph=False, batch_team=0, precond=PRECOND_NONE) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -241,6 +251,7 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
     o.batch_wgs_per_cu = int(batch_wgs_per_cu)
     o.batch_graph = 1 if batch_graph else 0
     o.batch_team = int(batch_team)
+    o.precond = int(precond)
     return o
 
 
@@ -490,3 +501,47 @@ def x0_predict_coarse(params, out_scale, factor: int, sweeps: int, A: Stencil, l
         C.byref(sc), _f32(logk, A.N, "logk"), _f64(f, A.N, "f"), _f64(x0, A.N, "x0"),
         1 if use_fallback else 0, C.byref(used), C.byref(o)), "x0_predict_coarse")
     return bool(used.value)
+
+
+# ---------------------------------------------------------------------------
+# ILU(0) right preconditioning (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def precond_workspace_bytes(A: Stencil, precond: int = PRECOND_ILU0) -> int:
+    sc = A.c_struct()
+    return int(load().sstep_precond_workspace_bytes(C.byref(sc), int(precond)))
+
+
+def ilu0_factor(A: Stencil, d=None, stream=None):
+    """Pivots of the ILU(0) factors of A: a float64 CUDA tensor [2N] (pivots,
+    then their reciprocals).  Raises on a zero pivot."""
+    import torch
+    if d is None:
+        d = torch.empty(2 * A.N, dtype=torch.float64, device="cuda")
+    sc = A.c_struct()
+    _check(load().sstep_ilu0_factor(C.byref(sc), _f64(d, 2 * A.N, "d"), _stream(stream)),
+           "ilu0_factor")
+    return d
+
+
+def ilu0_solve(A: Stencil, d, r, z=None, stream=None):
+    """z = M^{-1} r with M = L U the ILU(0) factors."""
+    import torch
+    if z is None:
+        z = torch.empty(A.N, dtype=torch.float64, device="cuda")
+    sc = A.c_struct()
+    _check(load().sstep_ilu0_solve(C.byref(sc), _f64(d, 2 * A.N, "d"), _f64(r, A.N, "r"),
+                                   _f64(z, A.N, "z"), _stream(stream)), "ilu0_solve")
+    return z
+
+
+def ilu0_mul(A: Stencil, d, x, u=None, stream=None):
+    """u = M x with M = L U the ILU(0) factors."""
+    import torch
+    if u is None:
+        u = torch.empty(A.N, dtype=torch.float64, device="cuda")
+    sc = A.c_struct()
+    _check(load().sstep_ilu0_mul(C.byref(sc), _f64(d, 2 * A.N, "d"), _f64(x, A.N, "x"),
+                                 _f64(u, A.N, "u"), _stream(stream)), "ilu0_mul")
+    return u
+
