@@ -398,15 +398,17 @@ def bench_paper2d(args):
     beta = 1, gamma = 50, x0 = 0.05 mod(i, 50)) on n x n grids, n in {64, 128,
     192, 256}, stopped at the paper's rule ||r||_2 < 1e-6, with the four
     settings of its Table 6.1 (Orthomin(4), 2-Orthomin(2), GMRES(10),
-    2-GMRES(5)), unpreconditioned.  Iterations of the HIP path and of the
-    oracle side by side (unless --no-cpu), and the solve times."""
+    2-GMRES(5)), unpreconditioned and with the paper's ILU(0) right
+    preconditioning (Sec. 5).  Iterations of the HIP path and of the oracle
+    side by side (unless --no-cpu), the solve times, and the time of one
+    preconditioner solve."""
     import numpy as np
     import torch
     from paper_2001_04886_amd import problems as PB
     from paper_2001_04886_amd import sstep as S
     dev = torch.device("cuda:0")
     settings = [("omin", 1, 4), ("omin", 2, 2), ("gmres", 1, 10), ("gmres", 2, 5)]
-    rows, cpu = [], None
+    rows, cpu, pc_us = [], None, {}
     for n in (64, 128, 192, 256):
         prob = PB.paper_problem(n)
         coef = torch.from_numpy(prob.coef).to(dev)
@@ -415,43 +417,62 @@ def bench_paper2d(args):
         tol = 1e-6 / float(np.linalg.norm(g))
         gd, x0d = torch.from_numpy(g).to(dev), torch.from_numpy(x0).to(dev)
         x = torch.empty_like(x0d)
-        for method, s, km in settings:
-            fn = S.gmres_solve if method == "gmres" else S.omin_solve
-            mth = S.METHOD_GMRES if method == "gmres" else S.METHOD_OMIN
-            ws = S.allocate_workspace(A, mth, s, km)
-            ts = []
-            for rep in range(args.warmup + max(args.steps, 3)):
-                x.copy_(x0d)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                info = fn(A, gd, x, s, km, tol, max_iters=20000, workspace=ws)
-                torch.cuda.synchronize()
-                if rep >= args.warmup:
-                    ts.append(time.perf_counter() - t0)
-            xh = x.cpu().numpy()
-            row = {"n": n, "method": method, "s": s, "k_or_m": km, "iters": info.iters,
-                   "matvecs": info.matvecs, "status": info.status,
-                   "resid_2norm": info.rel_resid * float(np.linalg.norm(g)),
-                   "max_err_vs_analytic": float(np.max(np.abs(xh - PB.paper_exact(n)))),
-                   "gpu_s": sorted(ts)[len(ts) // 2]}
-            if not args.no_cpu:
-                import oracle as O
-                Ao = O.Operator(2, n, n, coef=prob.coef)
-                t0 = time.perf_counter()
-                if method == "gmres":
-                    _, res = O.sgmres(Ao, g, x0, s, km, tol, max_blocks=20000)
-                else:
-                    _, res = O.somin(Ao, g, x0, s, km, tol, max_iters=20000)
-                row["oracle_iters"], row["oracle_s"] = res.iters, time.perf_counter() - t0
-                if n == 256 and (method, s) == ("gmres", 2):
-                    cpu = {"value": row["oracle_s"], "unit": "s", "cores": 1, "kind": "oracle",
-                           "sample": "the whole 256^2 2-GMRES(5) solve, one host thread"}
-            rows.append(row)
-            print(f"# paper n={n} {method} s={s} k/m={km}: iters {info.iters}"
-                  + (f" (oracle {row['oracle_iters']})" if "oracle_iters" in row else "")
-                  + f" gpu {row['gpu_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    head = next(r for r in rows if r["n"] == 256 and r["method"] == "gmres" and r["s"] == 2)
-    extra = {"results": rows}
+        # one preconditioner solve (events around 50 back-to-back launches)
+        d = S.ilu0_factor(A)
+        z = torch.empty_like(gd)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        S.ilu0_solve(A, d, gd, z)
+        e0.record()
+        for _ in range(50):
+            S.ilu0_solve(A, d, gd, z)
+        e1.record()
+        torch.cuda.synchronize()
+        pc_us[n] = e0.elapsed_time(e1) * 1e3 / 50
+        print(f"# paper n={n} ILU(0) solve {pc_us[n]:.1f} us", file=sys.stderr, flush=True)
+        for pc in (S.PRECOND_NONE, S.PRECOND_ILU0):
+            for method, s, km in settings:
+                fn = S.gmres_solve if method == "gmres" else S.omin_solve
+                mth = S.METHOD_GMRES if method == "gmres" else S.METHOD_OMIN
+                ws = S.allocate_workspace(A, mth, s, km, precond=pc)
+                ts = []
+                for rep in range(args.warmup + max(args.steps, 3)):
+                    x.copy_(x0d)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    info = fn(A, gd, x, s, km, tol, max_iters=20000, workspace=ws, precond=pc)
+                    torch.cuda.synchronize()
+                    if rep >= args.warmup:
+                        ts.append(time.perf_counter() - t0)
+                xh = x.cpu().numpy()
+                row = {"n": n, "precond": "ilu0" if pc else "none", "method": method, "s": s,
+                       "k_or_m": km, "iters": info.iters, "cycles": info.cycles,
+                       "matvecs": info.matvecs, "status": info.status,
+                       "resid_2norm": info.rel_resid * float(np.linalg.norm(g)),
+                       "max_err_vs_analytic": float(np.max(np.abs(xh - PB.paper_exact(n)))),
+                       "gpu_s": sorted(ts)[len(ts) // 2]}
+                if not args.no_cpu:
+                    import oracle as O
+                    Ao = O.Operator(2, n, n, coef=prob.coef)
+                    t0 = time.perf_counter()
+                    if method == "gmres":
+                        run = O.sgmres_ilu0 if pc else O.sgmres
+                        _, res = run(Ao, g, x0, s, km, tol, max_blocks=20000)
+                    else:
+                        run = O.somin_ilu0 if pc else O.somin
+                        _, res = run(Ao, g, x0, s, km, tol, max_iters=20000)
+                    row["oracle_iters"], row["oracle_s"] = res.iters, time.perf_counter() - t0
+                    if n == 256 and (method, s) == ("gmres", 2) and not pc:
+                        cpu = {"value": row["oracle_s"], "unit": "s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "the whole 256^2 2-GMRES(5) solve, one host thread"}
+                rows.append(row)
+                print(f"# paper n={n} {row['precond']} {method} s={s} k/m={km}: iters "
+                      f"{info.iters} cycles {info.cycles}"
+                      + (f" (oracle {row['oracle_iters']})" if "oracle_iters" in row else "")
+                      + f" gpu {row['gpu_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    head = next(r for r in rows if r["n"] == 256 and r["method"] == "gmres" and r["s"] == 2
+                and r["precond"] == "none")
+    extra = {"results": rows, "ilu0_solve_us": pc_us}
     if cpu:
         extra["cpu_baseline"] = cpu
     _line("2-step GMRES(5) time to ||r|| < 1e-6, paper eq. (9) 256^2", head["gpu_s"], "s", False,

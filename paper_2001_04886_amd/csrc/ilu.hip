@@ -11,16 +11,16 @@
 // factors.)
 //
 // Point (i, j) of a forward sweep depends on (i-1, j) and (i, j-1), so the
-// sweep runs over the anti-diagonals i + j (the hyperplane order that makes
-// the preconditioner vectorise).  One wave of 64 lanes: lane l owns the CPL
-// columns [l CPL, (l+1) CPL) and reaches row j at step j + l, one step after
-// its west neighbour lane; the west value moves between lanes with a
-// whole-wave DPP shift (no LDS, no barrier), the south value stays in the
-// lane's registers.  The backward sweep mirrors this from the north-east
-// corner.  Loads for step t + D are issued at step t (register ring), every
-// load and store is a raw buffer access whose out-of-grid lanes read 0 /
-// write nothing, so the sweep has no branches and no wait for loads that are
-// still in flight.
+// sweeps run over the anti-diagonals i + j (the hyperplane order that makes
+// the preconditioner vectorise): a point is reached one step after its west
+// and its south neighbour.  The factorisation (once per solve) runs on one
+// wave whose lanes own CPL adjacent columns each; the preconditioner solve
+// (once per matrix-powers level) spreads the columns over up to 16 waves, one
+// column per lane.  Neighbour values move between lanes by whole-wave DPP
+// shifts, loads are issued several steps ahead of use (register ring), and
+// every load and store is a raw buffer access whose out-of-grid lanes read 0
+// / write nothing, so the sweeps have no branches around memory operations
+// and no wait for loads still in flight.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -145,121 +145,115 @@ __global__ __launch_bounds__(kIluLanes) void k_ilu0_factor(StencilView A, double
 // ---------------------------------------------------------------------------
 // z = M^{-1} r.  Forward: (D + Lo) w = r, w written to z; backward:
 // (D + Up) z = D w, i.e. z_p = w_p - (a_e z_{p+1} + a_n z_{p+nx}) / d_p, in
-// place.  Each lane reads back only the points it wrote itself.
+// place.  One workgroup of ceil(nx / 64) waves, one column per lane: wave w
+// owns columns [64 w, 64 w + 64).  Inside a wave the west (east) value comes
+// from the neighbour lane by a DPP shift; between waves lane 63 (lane 0)
+// leaves it in an LDS ring that the next wave reads.  Wave w runs kIluLag
+// steps behind wave w - 1 (64 for the wavefront, kIluK more so that a
+// barrier, taken every kIluK steps, always separates the ring write from its
+// read), and loads run kIluK steps ahead of use.  Points outside the grid
+// compute 0 from zero inputs, so the coefficients need no boundary masks:
+// every neighbour value that a boundary coefficient meets is 0.  Each lane
+// reads back only the points it wrote itself.
 // ---------------------------------------------------------------------------
-template <int CPL, int D, bool VC>
-__global__ __launch_bounds__(kIluLanes) void k_ilu0_solve(StencilView A,
-                                                          const double* __restrict__ dinv,
-                                                          const double* __restrict__ r,
-                                                          double* __restrict__ z,
-                                                          const int* __restrict__ skip) {
+constexpr int kIluK = 8;              // steps between barriers = prefetch depth
+constexpr int kIluRing = 32;          // exchange slots per wave (>= 2 kIluK + 2)
+constexpr int kIluLag = 64 + kIluK;   // steps between neighbouring waves
+constexpr int kIluMaxWaves = 16;
+
+template <bool VC>
+__global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
+    StencilView A, const double* __restrict__ dinv, const double* __restrict__ r,
+    double* __restrict__ z, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int nx = A.nx, ny = A.ny, lane = threadIdx.x, i0 = lane * CPL;
-    const int nl = ilu_lanes(nx, CPL), T = ny + nl - 1;
+    __shared__ double xch[kIluMaxWaves][kIluRing];
+    const int nx = A.nx, ny = A.ny, nw = blockDim.x >> 6;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = 64 * w + l;
+    const bool col = i < nx;
+    const int T = ny + 63 + (nw - 1) * kIluLag;
     const unsigned nb = (unsigned)(A.N * 8);
     const __amdgpu_buffer_rsrc_t rw = coef_rsrc(A, 1), re = coef_rsrc(A, 2), rs = coef_rsrc(A, 3),
                                  rn = coef_rsrc(A, 4);
     const __amdgpu_buffer_rsrc_t ri = mpk_rsrc(dinv, nb), rr = mpk_rsrc(r, nb), rz = mpk_rsrc(z, nb);
-
-    double v[D][CPL], dv[D][CPL], a1[D][CPL], a2[D][CPL];
-    // forward step t: row j = t - lane
-    auto fetch_f = [&](int t, int u) {
-        const int j = t - lane;
-        const bool row = j >= 0 && j < ny;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int i = i0 + c;
-            const bool in = row && i < nx;
-            v[u][c] = mpk_ld<double>(rr, ofs(in, i, j, nx));
-            dv[u][c] = mpk_ld<double>(ri, ofs(in, i, j, nx));
-            if constexpr (VC) {
-                a1[u][c] = mpk_ld<double>(rw, ofs(in && i > 0, i, j, nx));
-                a2[u][c] = mpk_ld<double>(rs, ofs(in && j > 0, i, j, nx));
-            } else {
-                a1[u][c] = (in && i > 0) ? A.c[1] : 0.0;
-                a2[u][c] = (in && j > 0) ? A.c[3] : 0.0;
-            }
-        }
-    };
-    // backward step t: lane l (counted from the top, m = nl - 1 - l) reaches
-    // row j = ny - 1 - (t - m)
-    const int m = nl - 1 - lane;
-    auto fetch_b = [&](int t, int u) {
-        const int j = ny - 1 - (t - m);
-        const bool row = m >= 0 && j >= 0 && j < ny;
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int i = i0 + c;
-            const bool in = row && i < nx;
-            v[u][c] = mpk_ld<double>(rz, ofs(in, i, j, nx));
-            dv[u][c] = mpk_ld<double>(ri, ofs(in, i, j, nx));
-            if constexpr (VC) {
-                a1[u][c] = mpk_ld<double>(re, ofs(in && i < nx - 1, i, j, nx));
-                a2[u][c] = mpk_ld<double>(rn, ofs(in && j < ny - 1, i, j, nx));
-            } else {
-                a1[u][c] = (in && i < nx - 1) ? A.c[2] : 0.0;
-                a2[u][c] = (in && j < ny - 1) ? A.c[4] : 0.0;
-            }
-        }
+    auto at = [&](int j) { return (col && j >= 0 && j < ny) ? (unsigned)((j * nx + i) * 8) : kMpkOff; };
+    auto clear_ring = [&]() {
+        for (int k = threadIdx.x; k < kIluMaxWaves * kIluRing; k += blockDim.x)
+            (&xch[0][0])[k] = 0.0;
+        __syncthreads();
     };
 
-    // forward sweep
-    // each sweep starts D steps early on zeros (nothing stored, nothing in
-    // flight at the loop's entry; see k_ilu0_factor)
-    auto clear = [&]() {
-#pragma unroll
-        for (int u = 0; u < D; ++u)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) v[u][c] = dv[u][c] = a1[u][c] = a2[u][c] = 0.0;
+    double v[kIluK], dv[kIluK], a1[kIluK], a2[kIluK];
+    auto fetch = [&](bool fwd, int j, int u) {
+        const unsigned o = at(j);
+        v[u] = mpk_ld<double>(fwd ? rr : rz, o);
+        dv[u] = mpk_ld<double>(ri, o);
+        if constexpr (VC) {
+            a1[u] = mpk_ld<double>(fwd ? rw : re, o);
+            a2[u] = mpk_ld<double>(fwd ? rs : rn, o);
+        } else {
+            a1[u] = o != kMpkOff ? (fwd ? A.c[1] : A.c[2]) : 0.0;
+            a2[u] = o != kMpkOff ? (fwd ? A.c[3] : A.c[4]) : 0.0;
+        }
     };
-    clear();
-    double nb_row[CPL];  // value of the previous row in each owned column
+    // both sweeps start kIluK steps early on zeros: no load is in flight when
+    // a loop is entered, and every entry to its head sees the same loads
+    auto zero_ring = [&]() {
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) nb_row[c] = 0.0;
-    double edge = 0.0;
-    for (int t0 = -D; t0 < T; t0 += D) {
+        for (int u = 0; u < kIluK; ++u) v[u] = dv[u] = a1[u] = a2[u] = 0.0;
+    };
+
+    // forward sweep: wave w, lane l at step t is on row t - l - w kIluLag
+    clear_ring();
+    zero_ring();
+    {
+        const int off = l + w * kIluLag;
+        double below = 0.0, edge = 0.0, xp = 0.0;
+        for (int t0 = -kIluK; t0 < T; t0 += kIluK) {
 #pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int t = t0 + u;
-            const int j = t - lane;
-            const bool row = j >= 0 && j < ny;
-            double w = from_lane_below(edge);
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int i = i0 + c;
-                w = (v[u][c] - a2[u][c] * nb_row[c] - a1[u][c] * w) * dv[u][c];
-                mpk_st<double>(w, rz, ofs(row && i < nx, i, j, nx));
-                nb_row[c] = w;
+            for (int u = 0; u < kIluK; ++u) {
+                const int t = t0 + u, j = t - off;
+                const double dn = from_lane_below(edge);
+                const double west = l == 0 ? xp : dn;
+                const double val = (v[u] - a2[u] * below - a1[u] * west) * dv[u];
+                mpk_st<double>(val, rz, at(j));
+                below = val;
+                edge = val;
+                if (l == 63) xch[w][j & (kIluRing - 1)] = val;
+                fetch(true, j + kIluK, u);
+                // lane 0: the value of the previous wave for the next row
+                xp = w > 0 ? xch[w - 1][(t + 1 - w * kIluLag) & (kIluRing - 1)] : 0.0;
             }
-            edge = w;
-            fetch_f(t + D, u);
+            __syncthreads();
         }
     }
     // the backward sweep reads the forward result of the lane's own points;
     // the wait also drains the forward sweep's last (out-of-range) loads
     __threadfence_block();
-
-    // backward sweep, columns of a lane from the last to the first
-    clear();
+    clear_ring();
+    zero_ring();
+    // backward sweep, mirrored: wave w, lane l at step t is on row
+    // ny - 1 - (t - (63 - l) - (nw - 1 - w) kIluLag)
+    {
+        const int wm = nw - 1 - w, off = (63 - l) + wm * kIluLag;
+        double above = 0.0, edge = 0.0, xp = 0.0;
+        for (int t0 = -kIluK; t0 < T; t0 += kIluK) {
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) nb_row[c] = 0.0;
-    edge = 0.0;
-    for (int t0 = -D; t0 < T; t0 += D) {
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            const int t = t0 + u;
-            const int j = ny - 1 - (t - m);
-            const bool row = m >= 0 && j >= 0 && j < ny;
-            double e = from_lane_above(edge);
-#pragma unroll
-            for (int c = CPL - 1; c >= 0; --c) {
-                const int i = i0 + c;
-                e = v[u][c] - dv[u][c] * (a1[u][c] * e + a2[u][c] * nb_row[c]);
-                mpk_st<double>(e, rz, ofs(row && i < nx, i, j, nx));
-                nb_row[c] = e;
+            for (int u = 0; u < kIluK; ++u) {
+                const int t = t0 + u, j = ny - 1 - (t - off);
+                const double up = from_lane_above(edge);
+                const double east = l == 63 ? xp : up;
+                const double val = v[u] - dv[u] * (a1[u] * east + a2[u] * above);
+                mpk_st<double>(val, rz, at(j));
+                above = val;
+                edge = val;
+                if (l == 0) xch[w][j & (kIluRing - 1)] = val;
+                fetch(false, j - kIluK, u);
+                // lane 63: the value of the next wave for the next row
+                xp = w < nw - 1
+                         ? xch[w + 1][(ny - 1 - (t + 1 - wm * kIluLag)) & (kIluRing - 1)]
+                         : 0.0;
             }
-            edge = e;
-            fetch_b(t + D, u);
+            __syncthreads();
         }
     }
 }
@@ -335,9 +329,9 @@ bool ilu0_supported(const sstep_stencil& A) {
            (long long)A.nx * A.ny * 8 < (1LL << 31);
 }
 
-// Prefetch depth D (steps) per columns-per-lane and coefficient kind: the
-// memory operations of D steps (loads and stores, about 5 per point with
-// coefficient fields, 3 without) must fit the 63 the wait counter tracks.
+// Factorisation prefetch depth D (steps) per columns-per-lane and coefficient
+// kind: the memory operations of D steps (about 7 per point with coefficient
+// fields, 2 without) must fit the 63 the wait counter tracks.
 #define SSTEP_ILU_CASES(X) X(1, 8, 8) X(2, 4, 8) X(4, 2, 4) X(8, 1, 2) X(16, 1, 1)
 
 void ilu0_factor_launch(Ctx& c, const StencilView& v, double* d, double* dinv, int* bad) {
@@ -364,19 +358,11 @@ void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* dinv, const d
     // algorithmic bytes: r, 1/d (twice), the four neighbour coefficients, the
     // intermediate written and read, z written
     c.begin(SSTEP_K_MPK, (double)v.N * 8.0 * (v.coef ? 10.0 : 6.0));
-    switch (ilu_cpl(v.nx)) {
-#define SSTEP_S(C, DV, DC)                                                                         \
-    case C:                                                                                        \
-        if (v.coef)                                                                                \
-            hipLaunchKernelGGL((k_ilu0_solve<C, DV, true>), dim3(1), dim3(kIluLanes), 0, c.st, v,  \
-                               dinv, r, z, skip);                                                  \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_ilu0_solve<C, DC, false>), dim3(1), dim3(kIluLanes), 0, c.st, v, \
-                               dinv, r, z, skip);                                                  \
-        break;
-        SSTEP_ILU_CASES(SSTEP_S)
-#undef SSTEP_S
-    }
+    const dim3 block(64 * ((v.nx + 63) / 64));
+    if (v.coef)
+        hipLaunchKernelGGL(k_ilu0_solve<true>, dim3(1), block, 0, c.st, v, dinv, r, z, skip);
+    else
+        hipLaunchKernelGGL(k_ilu0_solve<false>, dim3(1), block, 0, c.st, v, dinv, r, z, skip);
     SSTEP_HIP(hipGetLastError());
     c.end();
 }

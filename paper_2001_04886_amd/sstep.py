@@ -261,12 +261,18 @@ def workspace_bytes(A: Stencil, method: int, s: int, k_or_m: int, precision: int
 
 
 def allocate_workspace(A: Stencil, method: int, s: int, k_or_m: int, precision: int = FP64,
-                       device="cuda"):
-    """A caller-owned workspace tensor (uint8) large enough for the solver."""
+                       device="cuda", precond: int = PRECOND_NONE):
+    """A caller-owned workspace tensor (uint8) large enough for the solver
+    (and for its preconditioner, if precond is set)."""
     import torch
     nb = workspace_bytes(A, method, s, k_or_m, precision)
     if nb == 0:
         raise SstepError("invalid arguments for workspace sizing")
+    if precond != PRECOND_NONE:
+        pb = precond_workspace_bytes(A, precond)
+        if pb == 0:
+            raise SstepError("preconditioner not supported for this operator")
+        nb += pb
     return torch.empty(nb + 256, dtype=torch.uint8, device=device)[: nb]
 
 
