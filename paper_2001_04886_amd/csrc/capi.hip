@@ -106,8 +106,13 @@ bool precond_ok(const sstep_stencil* A, const sstep_options* opt, int prec, int 
            basis == SSTEP_BASIS_MONOMIAL;
 }
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+size_t ilu0_sweep_bytes(const sstep_stencil& A) {
+    // intermediate, right-hand side, 1/d and (per-point coefficients) four
+    // neighbour coefficient planes
+    return align256((size_t)ilu0_sweep_points(make_view(A)) * 8) * (A.coef ? 7 : 3);
+}
 size_t ilu0_workspace(const sstep_stencil& A) {
-    return 4 * align256((size_t)grid_points(A) * 8) + 256;
+    return 4 * align256((size_t)grid_points(A) * 8) + ilu0_sweep_bytes(A) + 256;
 }
 // Right-preconditioned solve (Sec. 5): factor, u = M x, run the method on
 // A M^{-1} u = f with the preconditioner attached to the context, x = M^{-1} u.
@@ -121,16 +126,21 @@ int precond_solve(Ctx& c, const sstep_stencil& A, double* x, const sstep_options
     double* dinv = reinterpret_cast<double*>(pw + vb);
     double* u = reinterpret_cast<double*>(pw + 2 * vb);
     double* t = reinterpret_cast<double*>(pw + 3 * vb);
-    int* bad = reinterpret_cast<int*>(pw + 4 * vb);
+    const size_t sb = align256((size_t)ilu0_sweep_points(v) * 8);
+    double* wsk = reinterpret_cast<double*>(pw + 4 * vb);
+    double* rsk = reinterpret_cast<double*>(pw + 4 * vb + sb);
+    double* sk = reinterpret_cast<double*>(pw + 4 * vb + 2 * sb);
+    int* bad = reinterpret_cast<int*>(pw + 4 * vb + ilu0_sweep_bytes(A));
     ilu0_factor_launch(c, v, d, dinv, bad);
     int hb = 0;
     SSTEP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, c.st));
     SSTEP_HIP(hipStreamSynchronize(c.st));
     if (hb) return SSTEP_ERR_BREAKDOWN;
+    ilu0_skew_launch(c, v, dinv, sk);
     ilu0_mul_launch(c, v, d, dinv, x, u);
     sstep_options o2 = o;
     if (o2.sigma == 0.0) o2.sigma = 1.0;  // A M^{-1} is close to the identity
-    const Ilu0 P{d, dinv, t};
+    const Ilu0 P{d, dinv, t, sk, wsk, rsk};
     c.pc = &P;
     int st;
     try {
@@ -140,7 +150,7 @@ int precond_solve(Ctx& c, const sstep_stencil& A, double* x, const sstep_options
         throw;
     }
     c.pc = nullptr;
-    ilu0_solve_launch(c, v, dinv, u, x, nullptr);
+    ilu0_solve_launch(c, v, sk, wsk, rsk, u, x, nullptr);
     return st;
 }
 }  // namespace
@@ -265,7 +275,16 @@ int sstep_ilu0_solve(const sstep_stencil* A, const double* d, const double* r, d
         Ctx c;
         c.st = (hipStream_t)stream;
         const StencilView v = make_view(*A);
-        ilu0_solve_launch(c, v, d + v.N, r, z, nullptr);
+        // the sweeps read 1/d (and the coefficients) in their own layout
+        const size_t sb = align256((size_t)ilu0_sweep_points(v) * 8);
+        char* buf = nullptr;
+        SSTEP_HIP(hipMallocAsync((void**)&buf, ilu0_sweep_bytes(*A), c.st));
+        double* wsk = reinterpret_cast<double*>(buf);
+        double* rsk = reinterpret_cast<double*>(buf + sb);
+        double* sk = reinterpret_cast<double*>(buf + 2 * sb);
+        ilu0_skew_launch(c, v, d + v.N, sk);
+        ilu0_solve_launch(c, v, sk, wsk, rsk, r, z, nullptr);
+        SSTEP_HIP(hipFreeAsync(buf, c.st));
         return SSTEP_OK;
     });
 }

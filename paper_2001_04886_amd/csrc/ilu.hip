@@ -50,6 +50,13 @@ __device__ __forceinline__ double from_lane_above(double v) {
     return __longlong_as_double(((long long)hi << 32) | lo);
 }
 
+// Store through the caches (no nontemporal hint): the sweeps read back what
+// they wrote, and a store's completion gates the wait for every later load.
+__device__ __forceinline__ void ilu_st(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+
 // Buffer resource over coefficient plane q of a variable-coefficient stencil
 // (or an empty one: every access out of range).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t coef_rsrc(const StencilView& A, int q) {
@@ -129,8 +136,8 @@ __global__ __launch_bounds__(kIluLanes) void k_ilu0_factor(StencilView A, double
                 const double r = 1.0 / piv;
                 fail |= in && !(std::isfinite(piv) && piv != 0.0 && std::isfinite(r));
                 const double rv = in ? r : 0.0;
-                mpk_st<double>(piv, rd, ofs(in, i, j, nx));
-                mpk_st<double>(rv, ri, ofs(in, i, j, nx));
+                ilu_st(piv, rd, ofs(in, i, j, nx));
+                ilu_st(rv, ri, ofs(in, i, j, nx));
                 south[c] = rv;
                 west = rv;
             }
@@ -143,56 +150,137 @@ __global__ __launch_bounds__(kIluLanes) void k_ilu0_factor(StencilView A, double
 }
 
 // ---------------------------------------------------------------------------
-// z = M^{-1} r.  Forward: (D + Lo) w = r, w written to z; backward:
-// (D + Up) z = D w, i.e. z_p = w_p - (a_e z_{p+1} + a_n z_{p+nx}) / d_p, in
-// place.  One workgroup of ceil(nx / 64) waves, one column per lane: wave w
-// owns columns [64 w, 64 w + 64).  Inside a wave the west (east) value comes
-// from the neighbour lane by a DPP shift; between waves lane 63 (lane 0)
-// leaves it in an LDS ring that the next wave reads.  Wave w runs kIluLag
-// steps behind wave w - 1 (64 for the wavefront, kIluK more so that a
-// barrier, taken every kIluK steps, always separates the ring write from its
-// read), and loads run kIluK steps ahead of use.  Points outside the grid
-// compute 0 from zero inputs, so the coefficients need no boundary masks:
-// every neighbour value that a boundary coefficient meets is 0.  Each lane
-// reads back only the points it wrote itself.
+// z = M^{-1} r.  Forward: (D + Lo) w = r; backward: (D + Up) z = D w, i.e.
+// z_p = w_p - (a_e z_{p+1} + a_n z_{p+nx}) / d_p.  One workgroup of
+// ceil(nx / 64) waves, one column per lane: wave w owns columns
+// [64 w, 64 w + 64).  Inside a wave the west (east) value comes from the
+// neighbour lane by a DPP shift; between waves lane 63 (lane 0) leaves it in
+// an LDS ring that the next wave reads two steps before it needs it.  Wave w
+// runs kIluLag steps behind wave w - 1 (64 for the wavefront, kIluK + 1 more
+// so that a barrier, taken every kIluK steps, always separates the ring
+// write from that read), and loads run kIluK steps ahead of use.
+//
+// Sweep layout: the lanes of a wave sit on an anti-diagonal, 64 different
+// rows, so natural-order arrays cost a cache line per lane and access.
+// 1/d, the coefficients and the intermediate w are therefore kept with point
+// (i, j) at ((w * (ny + 63) + j + l) * 64 + l), i = 64 w + l: at every step
+// of either sweep the 64 lanes of a wave read one contiguous 512-byte row of
+// it.  r is copied into this layout and z out of it by two grid-wide kernels
+// around the sweeps (the backward sweep overwrites w with z in place).
+// Slots that are no grid point hold 0, and points outside the grid compute
+// 0, so the coefficients need no boundary masks: every neighbour value a
+// boundary coefficient meets is 0.
 // ---------------------------------------------------------------------------
 constexpr int kIluK = 8;              // steps between barriers = prefetch depth
 constexpr int kIluRing = 32;          // exchange slots per wave (>= 2 kIluK + 2)
-constexpr int kIluLag = 64 + kIluK;   // steps between neighbouring waves
+constexpr int kIluLag = 64 + kIluK + 1;  // steps between neighbouring waves
 constexpr int kIluMaxWaves = 16;
+
+__host__ __device__ __forceinline__ int sweep_rows(int ny) { return ny + 63; }
+
+// 1/d and (VC) the west, south, east, north coefficients into the sweep
+// layout: sk[k * P + slot], P = ilu0_sweep_points, k = 0..4.
+template <bool VC>
+__global__ __launch_bounds__(kThreads) void k_ilu0_skew(StencilView A, long long P,
+                                                        const double* __restrict__ dinv,
+                                                        double* __restrict__ sk) {
+    const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= P) return;
+    const int l = (int)(s & 63);
+    const long long q = s >> 6;
+    const int TS = sweep_rows(A.ny);
+    const int tr = (int)(q % TS), w = (int)(q / TS);
+    const int j = tr - l, i = 64 * w + l;
+    const bool ok = j >= 0 && j < A.ny && i < A.nx;
+    const long long p = ok ? (long long)j * A.nx + i : 0;
+    sk[s] = ok ? dinv[p] : 0.0;
+    if constexpr (VC) {
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) sk[k * P + s] = ok ? A.coef[k * A.N + p] : 0.0;
+    }
+}
+
+// x (natural order) into the sweep layout, 0 where a slot is no grid point.
+__global__ __launch_bounds__(kThreads) void k_ilu0_to_sweep(StencilView A, long long P,
+                                                            const double* __restrict__ x,
+                                                            double* __restrict__ xs,
+                                                            const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long s = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (s >= P) return;
+    const int l = (int)(s & 63);
+    const long long q = s >> 6;
+    const int TS = sweep_rows(A.ny);
+    const int j = (int)(q % TS) - l, i = 64 * (int)(q / TS) + l;
+    xs[s] = (j >= 0 && j < A.ny && i < A.nx) ? x[(long long)j * A.nx + i] : 0.0;
+}
+
+// The sweep layout back to natural order, one thread per grid point.
+__global__ __launch_bounds__(kThreads) void k_ilu0_from_sweep(StencilView A,
+                                                              const double* __restrict__ xs,
+                                                              double* __restrict__ x,
+                                                              const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= A.N) return;
+    const int i = (int)(p % A.nx), j = (int)(p / A.nx), l = i & 63;
+    x[p] = xs[((long long)(i >> 6) * sweep_rows(A.ny) + j + l) * 64 + l];
+}
 
 template <bool VC>
 __global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
-    StencilView A, const double* __restrict__ dinv, const double* __restrict__ r,
-    double* __restrict__ z, const int* __restrict__ skip) {
+    StencilView A, long long P, const double* __restrict__ sk, const double* __restrict__ rsk,
+    double* __restrict__ wsk, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    __shared__ double xch[kIluMaxWaves][kIluRing];
-    const int nx = A.nx, ny = A.ny, nw = blockDim.x >> 6;
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = 64 * w + l;
-    const bool col = i < nx;
+    // ring row kIluMaxWaves stays 0 (the west of wave 0 / east of the last
+    // wave); lanes that publish nothing write their own dummy slot instead
+    __shared__ double xch[kIluMaxWaves + 1][kIluRing];
+    __shared__ double dummy[kIluMaxWaves * 64];
+    const int ny = A.ny, nw = blockDim.x >> 6, TS = sweep_rows(ny);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     const int T = ny + 63 + (nw - 1) * kIluLag;
-    const unsigned nb = (unsigned)(A.N * 8);
-    const __amdgpu_buffer_rsrc_t rw = coef_rsrc(A, 1), re = coef_rsrc(A, 2), rs = coef_rsrc(A, 3),
-                                 rn = coef_rsrc(A, 4);
-    const __amdgpu_buffer_rsrc_t ri = mpk_rsrc(dinv, nb), rr = mpk_rsrc(r, nb), rz = mpk_rsrc(z, nb);
-    auto at = [&](int j) { return (col && j >= 0 && j < ny) ? (unsigned)((j * nx + i) * 8) : kMpkOff; };
+    const unsigned pb = (unsigned)(P * 8);
+    const __amdgpu_buffer_rsrc_t rr = mpk_rsrc(rsk, pb);
+    const __amdgpu_buffer_rsrc_t rd = mpk_rsrc(sk, pb), rws = mpk_rsrc(wsk, pb);
+    // coefficient planes in stencil order: 1 west, 2 east, 3 south, 4 north
+    const __amdgpu_buffer_rsrc_t rcw = mpk_rsrc(sk + (VC ? P : 0), VC ? pb : 0u),
+                                 rce = mpk_rsrc(sk + (VC ? 2 * P : 0), VC ? pb : 0u),
+                                 rcs = mpk_rsrc(sk + (VC ? 3 * P : 0), VC ? pb : 0u),
+                                 rcn = mpk_rsrc(sk + (VC ? 4 * P : 0), VC ? pb : 0u);
+    // sweep-layout offset of sweep row tr of this wave
+    const unsigned sbase = (unsigned)((w * TS * 64 + l) * 8);
+    auto sat = [&](int tr) {
+        return (unsigned)tr < (unsigned)TS ? sbase + (unsigned)tr * 512u : kMpkOff;
+    };
     auto clear_ring = [&]() {
-        for (int k = threadIdx.x; k < kIluMaxWaves * kIluRing; k += blockDim.x)
+        for (int k = threadIdx.x; k < (kIluMaxWaves + 1) * kIluRing; k += blockDim.x)
             (&xch[0][0])[k] = 0.0;
         __syncthreads();
     };
 
     double v[kIluK], dv[kIluK], a1[kIluK], a2[kIluK];
-    auto fetch = [&](bool fwd, int j, int u) {
-        const unsigned o = at(j);
-        v[u] = mpk_ld<double>(fwd ? rr : rz, o);
-        dv[u] = mpk_ld<double>(ri, o);
+    auto fetch_f = [&](int j, int u) {
+        const unsigned o = sat(j + l);
+        v[u] = mpk_ld<double>(rr, o);
+        dv[u] = mpk_ld<double>(rd, o);
         if constexpr (VC) {
-            a1[u] = mpk_ld<double>(fwd ? rw : re, o);
-            a2[u] = mpk_ld<double>(fwd ? rs : rn, o);
+            a1[u] = mpk_ld<double>(rcw, o);
+            a2[u] = mpk_ld<double>(rcs, o);
         } else {
-            a1[u] = o != kMpkOff ? (fwd ? A.c[1] : A.c[2]) : 0.0;
-            a2[u] = o != kMpkOff ? (fwd ? A.c[3] : A.c[4]) : 0.0;
+            a1[u] = A.c[1];  // times a neighbour value that is 0 off the grid
+            a2[u] = A.c[3];
+        }
+    };
+    auto fetch_b = [&](int j, int u) {
+        const unsigned o = sat(j + l);
+        v[u] = mpk_ld<double>(rws, o);
+        dv[u] = mpk_ld<double>(rd, o);
+        if constexpr (VC) {
+            a1[u] = mpk_ld<double>(rce, o);
+            a2[u] = mpk_ld<double>(rcn, o);
+        } else {
+            a1[u] = A.c[2];
+            a2[u] = A.c[4];
         }
     };
     // both sweeps start kIluK steps early on zeros: no load is in flight when
@@ -202,12 +290,16 @@ __global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
         for (int u = 0; u < kIluK; ++u) v[u] = dv[u] = a1[u] = a2[u] = 0.0;
     };
 
-    // forward sweep: wave w, lane l at step t is on row t - l - w kIluLag
+    // forward sweep: wave w, lane l at step t is on row j = t - l - w kIluLag,
+    // sweep row j + l = t - w kIluLag
     clear_ring();
     zero_ring();
     {
         const int off = l + w * kIluLag;
-        double below = 0.0, edge = 0.0, xp = 0.0;
+        double* const pub = l == 63 ? &xch[w][0] : &dummy[threadIdx.x];
+        const int pmask = l == 63 ? kIluRing - 1 : 0;
+        const double* const sub = &xch[w > 0 ? w - 1 : kIluMaxWaves][0];
+        double below = 0.0, edge = 0.0, xp = 0.0, xq = 0.0;
         for (int t0 = -kIluK; t0 < T; t0 += kIluK) {
 #pragma unroll
             for (int u = 0; u < kIluK; ++u) {
@@ -215,13 +307,14 @@ __global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
                 const double dn = from_lane_below(edge);
                 const double west = l == 0 ? xp : dn;
                 const double val = (v[u] - a2[u] * below - a1[u] * west) * dv[u];
-                mpk_st<double>(val, rz, at(j));
+                ilu_st(val, rws, sat(j + l));
                 below = val;
                 edge = val;
-                if (l == 63) xch[w][j & (kIluRing - 1)] = val;
-                fetch(true, j + kIluK, u);
-                // lane 0: the value of the previous wave for the next row
-                xp = w > 0 ? xch[w - 1][(t + 1 - w * kIluLag) & (kIluRing - 1)] : 0.0;
+                pub[j & pmask] = val;
+                fetch_f(j + kIluK, u);
+                // lane 0: the previous wave's value for the row two steps on
+                xp = xq;
+                xq = sub[(t + 2 - w * kIluLag) & (kIluRing - 1)];
             }
             __syncthreads();
         }
@@ -232,10 +325,13 @@ __global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
     clear_ring();
     zero_ring();
     // backward sweep, mirrored: wave w, lane l at step t is on row
-    // ny - 1 - (t - (63 - l) - (nw - 1 - w) kIluLag)
+    // j = ny - 1 - (t - (63 - l) - (nw - 1 - w) kIluLag)
     {
         const int wm = nw - 1 - w, off = (63 - l) + wm * kIluLag;
-        double above = 0.0, edge = 0.0, xp = 0.0;
+        double* const pub = l == 0 ? &xch[w][0] : &dummy[threadIdx.x];
+        const int pmask = l == 0 ? kIluRing - 1 : 0;
+        const double* const sub = &xch[w < nw - 1 ? w + 1 : kIluMaxWaves][0];
+        double above = 0.0, edge = 0.0, xp = 0.0, xq = 0.0;
         for (int t0 = -kIluK; t0 < T; t0 += kIluK) {
 #pragma unroll
             for (int u = 0; u < kIluK; ++u) {
@@ -243,15 +339,14 @@ __global__ __launch_bounds__(64 * kIluMaxWaves) void k_ilu0_solve(
                 const double up = from_lane_above(edge);
                 const double east = l == 63 ? xp : up;
                 const double val = v[u] - dv[u] * (a1[u] * east + a2[u] * above);
-                mpk_st<double>(val, rz, at(j));
+                ilu_st(val, rws, sat(j + l));
                 above = val;
                 edge = val;
-                if (l == 0) xch[w][j & (kIluRing - 1)] = val;
-                fetch(false, j - kIluK, u);
-                // lane 63: the value of the next wave for the next row
-                xp = w < nw - 1
-                         ? xch[w + 1][(ny - 1 - (t + 1 - wm * kIluLag)) & (kIluRing - 1)]
-                         : 0.0;
+                pub[j & pmask] = val;
+                fetch_b(j - kIluK, u);
+                // lane 63: the next wave's value for the row two steps on
+                xp = xq;
+                xq = sub[(ny - 1 - (t + 2 - wm * kIluLag)) & (kIluRing - 1)];
             }
             __syncthreads();
         }
@@ -325,8 +420,10 @@ int ilu_cpl(int nx) {
 }  // namespace
 
 bool ilu0_supported(const sstep_stencil& A) {
+    // byte offsets of the natural and of the sweep layout fit 31 bits
     return A.ndim == 2 && A.nx >= 1 && A.ny >= 1 && A.nx <= kIluMaxNx &&
-           (long long)A.nx * A.ny * 8 < (1LL << 31);
+           (long long)A.nx * A.ny * 8 < (1LL << 31) &&
+           (long long)((A.nx + 63) / 64) * 64 * (A.ny + 63) * 8 < (1LL << 31);
 }
 
 // Factorisation prefetch depth D (steps) per columns-per-lane and coefficient
@@ -353,16 +450,37 @@ void ilu0_factor_launch(Ctx& c, const StencilView& v, double* d, double* dinv, i
     c.end();
 }
 
-void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* dinv, const double* r,
-                       double* z, const int* skip) {
+long long ilu0_sweep_points(const StencilView& v) {
+    return (long long)((v.nx + 63) / 64) * sweep_rows(v.ny) * 64;
+}
+
+void ilu0_skew_launch(Ctx& c, const StencilView& v, const double* dinv, double* sk) {
+    const long long P = ilu0_sweep_points(v);
+    c.begin(SSTEP_K_MPK, (double)P * 8.0 * (v.coef ? 10.0 : 2.0));
+    const dim3 grid((unsigned)((P + kThreads - 1) / kThreads));
+    if (v.coef)
+        hipLaunchKernelGGL(k_ilu0_skew<true>, grid, dim3(kThreads), 0, c.st, v, P, dinv, sk);
+    else
+        hipLaunchKernelGGL(k_ilu0_skew<false>, grid, dim3(kThreads), 0, c.st, v, P, dinv, sk);
+    SSTEP_HIP(hipGetLastError());
+    c.end();
+}
+
+void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* sk, double* wsk,
+                       double* rsk, const double* r, double* z, const int* skip) {
     // algorithmic bytes: r, 1/d (twice), the four neighbour coefficients, the
     // intermediate written and read, z written
     c.begin(SSTEP_K_MPK, (double)v.N * 8.0 * (v.coef ? 10.0 : 6.0));
+    const long long P = ilu0_sweep_points(v);
+    hipLaunchKernelGGL(k_ilu0_to_sweep, dim3((unsigned)((P + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c.st, v, P, r, rsk, skip);
     const dim3 block(64 * ((v.nx + 63) / 64));
     if (v.coef)
-        hipLaunchKernelGGL(k_ilu0_solve<true>, dim3(1), block, 0, c.st, v, dinv, r, z, skip);
+        hipLaunchKernelGGL(k_ilu0_solve<true>, dim3(1), block, 0, c.st, v, P, sk, rsk, wsk, skip);
     else
-        hipLaunchKernelGGL(k_ilu0_solve<false>, dim3(1), block, 0, c.st, v, dinv, r, z, skip);
+        hipLaunchKernelGGL(k_ilu0_solve<false>, dim3(1), block, 0, c.st, v, P, sk, rsk, wsk, skip);
+    hipLaunchKernelGGL(k_ilu0_from_sweep, dim3((unsigned)((v.N + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, c.st, v, wsk, z, skip);
     SSTEP_HIP(hipGetLastError());
     c.end();
 }

@@ -68,6 +68,9 @@ struct Ilu0 {
     const double* d;
     const double* dinv;
     double* t;
+    const double* sk;  // 1/d (and the four neighbour coefficients) in the sweep layout
+    double* wsk;       // sweep intermediate in the sweep layout
+    double* rsk;       // right-hand side of a solve in the sweep layout
 };
 constexpr int kIluMaxNx = 1024;
 
@@ -365,8 +368,10 @@ inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, do
 // ILU(0) kernels (ilu.hip).
 bool ilu0_supported(const sstep_stencil& A);
 void ilu0_factor_launch(Ctx& c, const StencilView& v, double* d, double* dinv, int* bad);
-void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* dinv, const double* r,
-                       double* z, const int* skip);
+long long ilu0_sweep_points(const StencilView& v);
+void ilu0_skew_launch(Ctx& c, const StencilView& v, const double* dinv, double* sk);
+void ilu0_solve_launch(Ctx& c, const StencilView& v, const double* sk, double* wsk,
+                       double* rsk, const double* r, double* z, const int* skip);
 void ilu0_mul_launch(Ctx& c, const StencilView& v, const double* d, const double* dinv,
                      const double* x, double* u);
 void ilu0_level_launch(Ctx& c, const StencilView& v, const double* in, const double* in_scale,
@@ -393,7 +398,7 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
                 mpk_level_coefs(lev, basis, P, &a, &b, &g);
                 const double* in = Y + (long long)(lev - 1) * ldy;
                 const double* prev = lev >= 2 ? Y + (long long)(lev - 2) * ldy : nullptr;
-                ilu0_solve_launch(c, v, c.pc->dinv, in, c.pc->t, skip);
+                ilu0_solve_launch(c, v, c.pc->sk, c.pc->wsk, c.pc->rsk, in, c.pc->t, skip);
                 ilu0_level_launch(c, v, in, lev == 1 ? in_scale : nullptr, prev,
                                   lev == 2 ? in_scale : nullptr, a, b, g, c.pc->t,
                                   Y + (long long)lev * ldy, skip, vb * (lev == 1 ? 2.0 : 1.0));
@@ -457,7 +462,7 @@ template <typename TR>
 inline void launch_residual(Ctx& c, const StencilView& v, const double* f, const double* x, TR* r,
                             double* part) {
     if (c.pc) {  // x is the preconditioned unknown u: the residual is f - A M^{-1} u
-        ilu0_solve_launch(c, v, c.pc->dinv, x, c.pc->t, nullptr);
+        ilu0_solve_launch(c, v, c.pc->sk, c.pc->wsk, c.pc->rsk, x, c.pc->t, nullptr);
         x = c.pc->t;
     }
     c.begin(SSTEP_K_RESID, (double)v.N * (16.0 + sizeof(TR)));
