@@ -90,6 +90,9 @@ def _load():
     lib.orc_somin.restype = C.c_int
     lib.orc_somin.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, rp,
                               dp, C.c_int, C.POINTER(_OminDump)]
+    lib.orc_somin_ex.restype = C.c_int
+    lib.orc_somin_ex.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                 C.c_int, rp, dp, C.c_int, C.POINTER(_OminDump)]
     lib.orc_sgmres.restype = C.c_int
     lib.orc_sgmres.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, rp,
                                dp, C.c_int, C.POINTER(_CycleDump)]
@@ -214,8 +217,11 @@ def omin(A, f, x0, k, tol, max_iters=0, hist_cap=100000):
     return x, _res(res, hist)
 
 
-def somin(A, f, x0, s, k, tol, max_iters=0, basis=MONOMIAL, dump=False, hist_cap=100000):
-    """s-step Orthomin(k) (Sec. 3, Alg. 3.1).  Returns (x, Result[, P, AP, r])."""
+def somin(A, f, x0, s, k, tol, max_iters=0, basis=MONOMIAL, dump=False, hist_cap=100000,
+          mgs=False):
+    """s-step Orthomin(k) (Sec. 3, Alg. 3.1).  Returns (x, Result[, P, AP, r]).
+    mgs: the larger-s variant of Sec. 3 (A^T A-orthogonal direction blocks by
+    modified Gram-Schmidt, diagonal Scalar1/Scalar2)."""
     lib = _load()
     f = np.ascontiguousarray(f, dtype=np.float64)
     x = np.array(x0, dtype=np.float64, copy=True)
@@ -227,8 +233,8 @@ def somin(A, f, x0, s, k, tol, max_iters=0, basis=MONOMIAL, dump=False, hist_cap
         AP = np.zeros((k * s, A.N))
         r = np.zeros(A.N)
         d = _OminDump(_dp(P), _dp(AP), _dp(r), 0)
-    lib.orc_somin(A.ref, _dp(f), _dp(x), s, k, tol, max_iters, basis, C.byref(res), _dp(hist),
-                  hist_cap, C.byref(d) if d is not None else None)
+    lib.orc_somin_ex(A.ref, _dp(f), _dp(x), s, k, tol, max_iters, basis, 1 if mgs else 0,
+                     C.byref(res), _dp(hist), hist_cap, C.byref(d) if d is not None else None)
     out = (x, _res(res, hist))
     if dump:
         nb = d.nblocks

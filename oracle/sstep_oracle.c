@@ -507,6 +507,34 @@ int orc_omin(const orc_stencil *A, const double *f, double *x, int k, double tol
 /* s-step Orthomin(k) / s-step GCR -- Sec. 3, Alg. 3.1                       */
 /* ------------------------------------------------------------------------ */
 
+/* Larger-s variant (Sec. 3, after Alg. 3.1): the new direction block is made
+ * A^T A-orthogonal by modified Gram-Schmidt on the columns of AP (the same
+ * combinations applied to P), so W = AP^T AP becomes diagonal.  Column q,
+ * after its components along columns 0..q-1 are removed, keeps a fraction
+ * w_q / n0_q of its squared length n0_q; at or below ORC_RANK_TOL it is
+ * numerically dependent and is set to zero (the Cholesky of W then truncates
+ * the block there, the same rank rule as without the orthogonalisation). */
+static void mgs_ata(long long N, int s, double *P, double *AP)
+{
+    for (int q = 0; q < s; ++q) {
+        double *aq = AP + (long long)q * N, *pq = P + (long long)q * N;
+        const double n0 = dot(N, aq, aq);
+        for (int l = 0; l < q; ++l) {
+            const double *al = AP + (long long)l * N;
+            const double wl = dot(N, al, al);
+            if (!(wl > 0.0)) continue;
+            const double c = dot(N, al, aq) / wl;
+            axpy(N, -c, al, aq);
+            axpy(N, -c, P + (long long)l * N, pq);
+        }
+        const double w = dot(N, aq, aq);
+        if (!(w > ORC_RANK_TOL * n0) || !isfinite(w)) {
+            memset(aq, 0, sizeof(double) * N);
+            memset(pq, 0, sizeof(double) * N);
+        }
+    }
+}
+
 /* One s-step iteration i:
  *   W_i = AP_i^T AP_i, m_i = AP_i^T r_i            (step 1)
  *   W_i a_i = m_i                                   (step 2, Scalar1)
@@ -519,6 +547,13 @@ int orc_omin(const orc_stencil *A, const double *f, double *x, int k, double tol
 int orc_somin(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
               int max_iters, int basis, orc_result *res, double *hist, int hist_cap,
               orc_omin_dump *dump)
+{
+    return orc_somin_ex(A, f, x, s, k, tol, max_iters, basis, 0, res, hist, hist_cap, dump);
+}
+
+int orc_somin_ex(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
+                 int max_iters, int basis, int mgs, orc_result *res, double *hist, int hist_cap,
+                 orc_omin_dump *dump)
 {
     const long long N = orc_size(A);
     if (N <= 0 || s < 1 || s > 16 || k < 1 || tol < 0.0) {
@@ -572,6 +607,7 @@ int orc_somin(const orc_stencil *A, const double *f, double *x, int s, int k, do
         if (it >= max_iters) break;
         ++cycles;
         BUILD_R_AR(P, AP); /* P_0 = R_0, AP_0 = AR_0 in slot 0 */
+        if (mgs) mgs_ata(N, s, P, AP);
         int i = 0;
         for (;;) {
             int si = i % k;
@@ -623,6 +659,7 @@ int orc_somin(const orc_stencil *A, const double *f, double *x, int s, int k, do
                         axpy(N, Bj[q + l * s], APj + (long long)q * N, APn + (long long)l * N);
                     }
             }
+            if (mgs) mgs_ata(N, s, Pn, APn);
             int sn = (i + 1) % k;
             memcpy(P + sn * sN, Pn, sizeof(double) * sN);
             memcpy(AP + sn * sN, APn, sizeof(double) * sN);

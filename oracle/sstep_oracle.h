@@ -87,6 +87,12 @@ int orc_omin(const orc_stencil *A, const double *f, double *x, int k, double tol
 int orc_somin(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
               int max_iters, int basis, orc_result *res, double *hist, int hist_cap,
               orc_omin_dump *dump);
+/* orc_somin with mgs = 1: every new direction block is made A^T A-orthogonal
+ * by modified Gram-Schmidt (Sec. 3, the larger-s variant), so Scalar1 and
+ * Scalar2 see diagonal W. */
+int orc_somin_ex(const orc_stencil *A, const double *f, double *x, int s, int k, double tol,
+                 int max_iters, int basis, int mgs, orc_result *res, double *hist, int hist_cap,
+                 orc_omin_dump *dump);
 int orc_sgmres(const orc_stencil *A, const double *f, double *x, int s, int m, double tol,
                int max_blocks, int basis, orc_result *res, double *hist, int hist_cap,
                orc_cycle_dump *dump);
