@@ -470,9 +470,37 @@ def bench_paper2d(args):
                       f"{info.iters} cycles {info.cycles}"
                       + (f" (oracle {row['oracle_iters']})" if "oracle_iters" in row else "")
                       + f" gpu {row['gpu_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # larger s: s-step Orthomin(1) with and without the A^T A-orthogonal
+    # blocks of Sec. 3 (orth = MGS), 256^2, unpreconditioned
+    n = 256
+    prob = PB.paper_problem(n)
+    coef = torch.from_numpy(prob.coef).to(dev)
+    A = S.Stencil.from_problem(prob, coef)
+    g, x0 = PB.paper_rhs(n), PB.paper_x0(prob.N)
+    tol = 1e-6 / float(np.linalg.norm(g))
+    gd, x0d = torch.from_numpy(g).to(dev), torch.from_numpy(x0).to(dev)
+    x = torch.empty_like(x0d)
+    large_s = []
+    for s in (4, 8, 12, 16):
+        for orth in (S.ORTH_CHOL, S.ORTH_MGS):
+            ts = []
+            for rep in range(args.warmup + max(args.steps, 3)):
+                x.copy_(x0d)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = S.omin_solve(A, gd, x, s, 1, tol, max_iters=20000, orth=orth)
+                torch.cuda.synchronize()
+                if rep >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+            row = {"n": n, "s": s, "k": 1, "orth": "mgs" if orth else "chol",
+                   "iters": info.iters, "cycles": info.cycles, "status": info.status,
+                   "gpu_s": sorted(ts)[len(ts) // 2]}
+            large_s.append(row)
+            print(f"# paper n={n} s-Omin s={s} k=1 {row['orth']}: iters {info.iters} restarts "
+                  f"{info.cycles - 1} gpu {row['gpu_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     head = next(r for r in rows if r["n"] == 256 and r["method"] == "gmres" and r["s"] == 2
                 and r["precond"] == "none")
-    extra = {"results": rows, "ilu0_solve_us": pc_us}
+    extra = {"results": rows, "ilu0_solve_us": pc_us, "omin_large_s": large_s}
     if cpu:
         extra["cpu_baseline"] = cpu
     _line("2-step GMRES(5) time to ||r|| < 1e-6, paper eq. (9) 256^2", head["gpu_s"], "s", False,

@@ -66,6 +66,7 @@ enum { SSTEP_BASIS_MONOMIAL = 0, SSTEP_BASIS_CHEBYSHEV = 1 };
 enum { SSTEP_FP64 = 0, SSTEP_MIXED = 1 };
 enum { SSTEP_METHOD_OMIN = 0, SSTEP_METHOD_GMRES = 1 };
 enum { SSTEP_PRECOND_NONE = 0, SSTEP_PRECOND_ILU0 = 1 };
+enum { SSTEP_ORTH_CHOL = 0, SSTEP_ORTH_MGS = 1 };
 
 typedef struct {
     int32_t max_iters;    /* s-Omin: s-step iterations; s-GMRES: s-blocks over all cycles;
@@ -97,6 +98,14 @@ typedef struct {
        A caller-owned workspace must hold sstep_workspace_bytes() +
        sstep_precond_workspace_bytes() bytes. */
     int32_t precond;
+    /* s-Omin only (ERR_ARG for s-GMRES): SSTEP_ORTH_CHOL solves Scalar1 /
+       Scalar2 with the Cholesky factor of W (the paper's Alg. 3.1);
+       SSTEP_ORTH_MGS makes every new direction block A^T A-orthogonal by
+       modified Gram-Schmidt first, so W is diagonal -- the variant Sec. 3
+       proposes for larger s.  A column whose remaining squared length falls
+       to 1e-14 of its length before the block's orthogonalisation is set to
+       zero (the block is truncated there). */
+    int32_t orth;
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */

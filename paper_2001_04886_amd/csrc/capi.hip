@@ -197,7 +197,8 @@ int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s,
         s > kMaxS || m < 1 || (long long)m * s > 2048 ||
         !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
         (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
-        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0))) ||
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0) ||
+                 opt->orth != SSTEP_ORTH_CHOL)) ||
         !precond_ok(A, opt, prec, basis)) {
         if (info) std::memset(info, 0, sizeof(*info));
         return set_status(info, SSTEP_ERR_ARG);
@@ -223,7 +224,8 @@ int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, 
     if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
         s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
         prec != SSTEP_FP64 || (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
-        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0))) ||
+        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) ||
+                 (opt->orth != SSTEP_ORTH_CHOL && opt->orth != SSTEP_ORTH_MGS))) ||
         !precond_ok(A, opt, prec, basis)) {
         if (info) std::memset(info, 0, sizeof(*info));
         return set_status(info, SSTEP_ERR_ARG);
@@ -310,6 +312,7 @@ static int batch_args_ok(int nsys, const sstep_stencil* A, const double* const* 
         return 0;
     if (opt) {
         if (opt->precision != SSTEP_FP64 || opt->basis != SSTEP_BASIS_MONOMIAL ||
+            opt->precond != SSTEP_PRECOND_NONE || opt->orth != SSTEP_ORTH_CHOL ||
             opt->max_iters < 0 || !(opt->sigma >= 0.0))
             return 0;
         if (opt->batch_threads != 0 && opt->batch_threads != 256 && opt->batch_threads != 512 &&

@@ -19,6 +19,12 @@
 //   Gram     AP_j^T Y for the window                         (step 6)
 //   scalar   B_j = -W_j^{-1} (AP_j^T AR)                     (Scalar2)
 //   update   P_{i+1} = R + sum P_j B_j;  AP_{i+1} = AR + sum AP_j B_j (8-9)
+// With orth = SSTEP_ORTH_MGS every new block (P, AP) is then made
+// A^T A-orthogonal by modified Gram-Schmidt on the device (the larger-s
+// variant of Sec. 3): for q = 0..s-1 one Gram of AP_q against AP_q..AP_{s-1},
+// one scalar kernel for the coefficients and the dependence test, and one
+// update each of P_q..P_{s-1} and AP_q..AP_{s-1}.  W of the block is then
+// diagonal, and the Cholesky of Scalar1 / Scalar2 reduces to it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +45,9 @@ struct OmState {
     int it, done, conv, err;
     double rnorm, est;
     double coef_x[kMaxS], coef_r[kMaxS];
+    // modified Gram-Schmidt: coefficient row of the current step, and per
+    // column the squared length removed by the steps so far
+    double mgs_row[kMaxS], mgs_removed[kMaxS];
 };
 
 struct OmArrays {
@@ -193,6 +202,30 @@ __global__ __launch_bounds__(kThreads) void k_om_step2(OmArrays a, int nfill) {
     }
 }
 
+// MGS step q on the block whose Gram row G = AP_q^T [AP_q .. AP_{s-1}] is in
+// Gout: w = G[0] is the squared length of AP_q after its components along
+// AP_0..AP_{q-1} were removed, n0 = w + (removed) its length before.  Column
+// q is kept if w > rank_tol * n0 (else it is numerically dependent and set to
+// zero); the coefficient row for columns q..s-1 is [keep - 1, -G[l]/w ...].
+__global__ __launch_bounds__(64) void k_om_mgs(OmArrays a, int q) {
+    OmState* st = a.st;
+    if (st->done || threadIdx.x != 0) return;
+    const int s = st->s;
+    const double* G = a.Gout;
+    if (q == 0)
+        for (int l = 0; l < s; ++l) st->mgs_removed[l] = 0.0;
+    const double w = G[0];
+    const double n0 = w + st->mgs_removed[q];
+    const bool keep = std::isfinite(w) && w > st->rank_tol * n0;
+    st->mgs_row[0] = keep ? 0.0 : -1.0;
+    for (int l = q + 1; l < s; ++l) {
+        const double g = G[l - q];
+        const double c = keep ? g / w : 0.0;
+        st->mgs_row[l - q] = -c;
+        st->mgs_removed[l] += c * g;
+    }
+}
+
 struct OmLayout {
     long long N, ld;
     int s, k;
@@ -219,7 +252,7 @@ static OmLayout om_layout(const sstep_stencil& A, int s, int k) {
     L.off_coefP = take(sizeof(double) * (size_t)(k * s) * s);
     L.off_coefAP = take(sizeof(double) * (size_t)(s + 1 + k * s) * s);
     L.off_Wf = take(sizeof(GramFactor) * k);
-    size_t gp = gram_partial_doubles(L.N, s, s + 1);
+    size_t gp = std::max(gram_partial_doubles(L.N, s, s + 1), gram_partial_doubles(L.N, 1, s));
     for (int nf = 1; nf <= k; ++nf) gp = std::max(gp, gram_partial_doubles(L.N, nf * s, s + 1));
     L.off_gpart = take(sizeof(double) * gp);
     L.off_npart = take(sizeof(double) * (size_t)std::max<long long>(update_blocks(L.N), norm_blocks(L.N)));
@@ -303,6 +336,26 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
         SSTEP_HIP(hipMemcpyAsync(&hs, dst, sizeof(OmState), hipMemcpyDeviceToHost, c.st));
         SSTEP_HIP(hipStreamSynchronize(c.st));
     };
+    // A^T A-orthogonalise direction block `slot` in place (SSTEP_ORTH_MGS)
+    const bool mgs = opt.orth == SSTEP_ORTH_MGS;
+    auto orthogonalise = [&](int slot) {
+        double* Pb = Pr + (long long)slot * s * ld;
+        double* APb = APr + (long long)slot * s * ld;
+        for (int q = 0; q < s; ++q) {
+            double* Pq = Pb + (long long)q * ld;
+            double* APq = APb + (long long)q * ld;
+            launch_gram<double>(c, APq, ld, 1, APq, ld, s - q, (const double*)nullptr, 0, 0, N,
+                                gpart, a.Gout, done, SSTEP_K_VEC);
+            scalar(k_om_mgs, 64, q);
+            // columns q..s-1 += column q x row (column q itself: kept or zeroed)
+            launch_update<double, double, double, double, false>(
+                c, N, Pq, ld, Pq, ld, 1, nullptr, dst->mgs_row, Pq, ld, s - q, nullptr, done,
+                (2.0 * (s - q) + 1) * vb, SSTEP_K_VEC);
+            launch_update<double, double, double, double, false>(
+                c, N, APq, ld, APq, ld, 1, nullptr, dst->mgs_row, APq, ld, s - q, nullptr, done,
+                (2.0 * (s - q) + 1) * vb, SSTEP_K_VEC);
+        }
+    };
     // R_0, AR_0 from the current r (Y[:,0]) into slot 0
     auto start_recurrence = [&]() {
         launch_mpk<double>(c, v, Y, ld, s, opt.basis, P, nullptr, done);
@@ -313,6 +366,7 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
         launch_update<double, double, double, double, false>(
             c, N, (const double*)nullptr, 0, Y, ld, s + 1, nullptr, a.coefAP, APr, ld, s, nullptr,
             done, (2 * s + 1) * vb);
+        if (mgs) orthogonalise(0);
     };
 
     true_residual();
@@ -360,6 +414,7 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
                     c, N, (const double*)nullptr, 0, Y, ld, s + 1 + nfill * s, nullptr, a.coefAP,
                     APr + (long long)nslot * s * ld, ld, s, nullptr, done,
                     (2 * s + 1 + nfill * s) * vb);
+                if (mgs) orthogonalise(nslot);
             }
             read_state();
             const int ran = hs.it - it0;

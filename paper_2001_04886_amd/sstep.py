@@ -21,6 +21,7 @@ MONOMIAL, CHEBYSHEV = 0, 1
 FP64, MIXED = 0, 1
 METHOD_OMIN, METHOD_GMRES = 0, 1
 PRECOND_NONE, PRECOND_ILU0 = 0, 1
+ORTH_CHOL, ORTH_MGS = 0, 1
 K_MPK, K_GRAM, K_UPDATE, K_RESID, K_SCALAR, K_VEC, K_NCLASS = 0, 1, 2, 3, 4, 5, 6
 KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar", "vec")
 
@@ -49,7 +50,7 @@ class OptionsC(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("batch_threads", C.c_int32),
                 ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
-                ("batch_team", C.c_int32), ("precond", C.c_int32)]
+                ("batch_team", C.c_int32), ("precond", C.c_int32), ("orth", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -234,7 +235,8 @@ def _stream(stream=None) -> int:
 
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
             workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
-            batch_graph=False, batch_team=0, precond=PRECOND_NONE) -> OptionsC:
+            batch_graph=False, batch_team=0, precond=PRECOND_NONE,
+            orth=ORTH_CHOL) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -252,6 +254,7 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
     o.batch_graph = 1 if batch_graph else 0
     o.batch_team = int(batch_team)
     o.precond = int(precond)
+    o.orth = int(orth)
     return o
 
 

@@ -1,0 +1,92 @@
+"""GPU parity of the larger-s s-step Orthomin variant (Sec. 3: direction
+blocks made A^T A-orthogonal by modified Gram-Schmidt, orth = ORTH_MGS)
+through the C ABI against the FP64 oracle: fixed work on the paper's eq. (9)
+problem and on a 3-D constant-coefficient problem, converged runs at large s
+with the paper's stopping rule, a dependent block, and argument errors."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2001_04886_amd import problems as PB
+from paper_2001_04886_amd import sstep as S
+from helpers import operator
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def paper_pair(n):
+    pr = PB.paper_problem(n)
+    coef = torch.from_numpy(pr.coef).cuda()
+    return pr, operator(pr), S.Stencil.from_problem(pr, coef), coef
+
+
+def run(Ag, Ao, g, x0, s, k, tol, cap):
+    xd = torch.from_numpy(x0.copy()).cuda()
+    info = S.omin_solve(Ag, torch.from_numpy(g).cuda(), xd, s, k, tol, max_iters=cap,
+                        orth=S.ORTH_MGS)
+    xo, res = O.somin(Ao, g, x0, s, k, tol, max_iters=cap, mgs=True)
+    torch.cuda.synchronize()
+    return xd.cpu().numpy(), info, xo, res
+
+
+@pytest.mark.parametrize("s,k,bound", [(2, 2, 1e-9), (4, 1, 1e-9), (8, 2, 1e-8), (12, 1, 1e-6)])
+def test_fixed_work_paper_problem(s, k, bound):
+    print(f"omin mgs fixed work s={s} k={k}", flush=True)
+    pr, Ao, Ag, keep = paper_pair(48)
+    g, x0 = PB.paper_rhs(48), PB.paper_x0(pr.N)
+    xg, info, xo, res = run(Ag, Ao, g, x0, s, k, 0.0, 8)
+    assert info.iters == res.iters == 8
+    assert rel(xg, xo) <= bound, rel(xg, xo)
+
+
+def test_fixed_work_3d():
+    print("omin mgs fixed work 3-D", flush=True)
+    pr = PB.convdiff(3, 20, 20.0, ny=18, nz=17)
+    Ao = operator(pr)
+    Ag = S.Stencil.from_problem(pr)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(pr.N)
+    xg, info, xo, res = run(Ag, Ao, f, np.zeros(pr.N), 6, 2, 0.0, 6)
+    assert info.iters == res.iters == 6
+    assert rel(xg, xo) <= 1e-9, rel(xg, xo)
+
+
+@pytest.mark.parametrize("s", [8, 12, 16])
+def test_converged_large_s(s):
+    print(f"omin mgs converged s={s}", flush=True)
+    n = 64
+    pr, Ao, Ag, keep = paper_pair(n)
+    g, x0 = PB.paper_rhs(n), PB.paper_x0(pr.N)
+    tol = 1e-6 / np.linalg.norm(g)
+    xg, info, xo, res = run(Ag, Ao, g, x0, s, 1, tol, 5000)
+    assert info.status == S.OK and res.status == O.OK and info.rel_resid <= tol
+    assert abs(info.iters - res.iters) <= max(2, 0.1 * res.iters), (info.iters, res.iters)
+    u = PB.paper_exact(n)
+    eg, eo = np.max(np.abs(xg - u)), np.max(np.abs(xo - u))
+    assert abs(eg - eo) <= 1e-3 * eo, (eg, eo)
+
+
+def test_dependent_block():
+    print("omin mgs dependent block", flush=True)
+    A = S.Stencil(2, 5, 4, 1, (1.0, 0, 0, 0, 0, 0, 0))
+    g = torch.linspace(1.0, 2.0, 20, dtype=torch.float64, device="cuda")
+    x = torch.zeros(20, dtype=torch.float64, device="cuda")
+    info = S.omin_solve(A, g, x, 4, 1, 1e-12, max_iters=5, orth=S.ORTH_MGS)
+    torch.cuda.synchronize()
+    assert info.status == S.OK and info.iters == 1
+    np.testing.assert_allclose(x.cpu().numpy(), g.cpu().numpy(), rtol=1e-13)
+
+
+def test_argument_errors():
+    print("omin mgs argument errors", flush=True)
+    pr, Ao, Ag, keep = paper_pair(16)
+    g = torch.from_numpy(PB.paper_rhs(16)).cuda()
+    x = torch.zeros(pr.N, dtype=torch.float64, device="cuda")
+    assert S.gmres_solve(Ag, g, x, 2, 5, 1e-8, orth=S.ORTH_MGS).status == S.ERR_ARG
+    assert S.omin_solve(Ag, g, x, 2, 2, 1e-8, orth=5).status == S.ERR_ARG
