@@ -106,6 +106,10 @@ typedef struct {
        to 1e-14 of its length before the block's orthogonalisation is set to
        zero (the block is truncated there). */
     int32_t orth;
+    /* s-GMRES: 1 captures the launches of a restart cycle in a hipGraph on
+       first use and replays it for every later cycle (fewer launch gaps on
+       small grids); ignored with profile = 1 */
+    int32_t graph;
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */

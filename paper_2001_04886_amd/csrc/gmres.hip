@@ -24,6 +24,8 @@
 // Krylov space breaks down; the host synchronises once per cycle.
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -485,6 +487,33 @@ size_t gmres_workspace_bytes(const sstep_stencil& A, int s, int m, int precision
 }
 
 template <typename T>
+static void gmres_enqueue_cycle(Ctx& c, const StencilView& v, GmArrays& a, GmState* dst, T* basis,
+                                long long N, long long ld, int s, int K, int nb,
+                                const sstep_options& opt, const OpParams& P, double* gpart,
+                                double* npart, int nnpart, double vb, double* x,
+                                const std::function<void()>& residual_and_start);
+
+// A captured restart cycle (opt.graph): graph, executable, the private
+// capture stream and the block count it was captured for.
+struct CycleGraph {
+    bool on = false;
+    int nb = -1;
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void reset() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (g) (void)hipGraphDestroy(g);
+        if (cs) (void)hipStreamDestroy(cs);
+        exec = nullptr;
+        g = nullptr;
+        cs = nullptr;
+        nb = -1;
+    }
+    ~CycleGraph() { reset(); }
+};
+
+template <typename T>
 static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* x, int s, int m,
                      double tol, const sstep_options& opt, sstep_info* info, char* ws,
                      const GmLayout& L) {
@@ -575,6 +604,13 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
     residual_and_start();
     read_state();
     c.harvest(0);
+    const std::function<void()> ras = residual_and_start;
+    auto enqueue_cycle = [&](int nb) {
+        gmres_enqueue_cycle<T>(c, v, a, dst, basis, N, ld, s, K, nb, opt, P, gpart, npart, nnpart,
+                               vb, x, ras);
+    };
+    CycleGraph graph;
+    graph.on = opt.graph != 0 && !c.profile;
     int matvecs = 1, cycles = 0;
     int status = SSTEP_NOT_CONVERGED;
     double last_est = ret.beta;
@@ -584,6 +620,63 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
         const int nb = std::min(m, max_blocks - ret.blocks_total);
         if (nb <= 0) { status = SSTEP_NOT_CONVERGED; break; }
         ++cycles;
+        if (graph.on) {
+            // the launches of a cycle depend only on nb: capture them once on
+            // a private stream (capture needs one), replay every cycle
+            if (!graph.exec || graph.nb != nb) {
+                graph.reset();
+                (void)device_cus();  // device queries happen before the capture
+                SSTEP_HIP(hipStreamCreateWithFlags(&graph.cs, hipStreamNonBlocking));
+                SSTEP_HIP(hipStreamBeginCapture(graph.cs, hipStreamCaptureModeThreadLocal));
+                const hipStream_t user = c.st;
+                c.st = graph.cs;
+                try {
+                    enqueue_cycle(nb);
+                } catch (...) {
+                    c.st = user;
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(graph.cs, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                c.st = user;
+                SSTEP_HIP(hipStreamEndCapture(graph.cs, &graph.g));
+                SSTEP_HIP(hipGraphInstantiate(&graph.exec, graph.g, nullptr, nullptr, 0));
+                graph.nb = nb;
+            }
+            SSTEP_HIP(hipGraphLaunch(graph.exec, c.st));
+        } else {
+            enqueue_cycle(nb);
+        }
+        const int before = ret.blocks_total;
+        read_state();
+        const int ran = ret.blocks_total - before;
+        matvecs += ran * s + 1;
+        c.harvest(ran);
+        last_est = ret.est;
+    }
+    if (info) {
+        info->iters = ret.blocks_total;
+        info->cycles = cycles;
+        info->matvecs = matvecs;
+        info->rel_resid = ret.fnorm > 0 ? ret.beta / ret.fnorm : ret.beta;
+        info->rel_resid_est = ret.fnorm > 0 ? last_est / ret.fnorm : last_est;
+        info->sigma = P.sigma;
+        info->cheb_centre = P.cc;
+        info->cheb_half_width = P.cd;
+    }
+    return status;
+}
+
+// The launches of one restart cycle of nb blocks, then the least-squares
+// solve, the solution update and the next cycle's true residual.
+template <typename T>
+static void gmres_enqueue_cycle(Ctx& c, const StencilView& v, GmArrays& a, GmState* dst, T* basis,
+                                long long N, long long ld, int s, int K, int nb,
+                                const sstep_options& opt, const OpParams& P, double* gpart,
+                                double* npart, int nnpart, double vb, double* x,
+                                const std::function<void()>& residual_and_start) {
+    {
         const int* done = &dst->done;
         for (int kb = 0; kb < nb; ++kb) {
             c.cur_block = kb;
@@ -627,24 +720,7 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
                                                         a.coefA, x, 0, 1, nullptr, &dst->skip_asm,
                                                         0.0, SSTEP_K_VEC);
         residual_and_start();
-        const int before = ret.blocks_total;
-        read_state();
-        const int ran = ret.blocks_total - before;
-        matvecs += ran * s + 1;
-        c.harvest(ran);
-        last_est = ret.est;
     }
-    if (info) {
-        info->iters = ret.blocks_total;
-        info->cycles = cycles;
-        info->matvecs = matvecs;
-        info->rel_resid = ret.fnorm > 0 ? ret.beta / ret.fnorm : ret.beta;
-        info->rel_resid_est = ret.fnorm > 0 ? last_est / ret.fnorm : last_est;
-        info->sigma = P.sigma;
-        info->cheb_centre = P.cc;
-        info->cheb_half_width = P.cd;
-    }
-    return status;
 }
 
 int gmres_solve_impl(Ctx& c, const sstep_stencil& A, const double* f, double* x, int s, int m,

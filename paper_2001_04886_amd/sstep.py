@@ -50,7 +50,8 @@ class OptionsC(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("batch_threads", C.c_int32),
                 ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
-                ("batch_team", C.c_int32), ("precond", C.c_int32), ("orth", C.c_int32)]
+                ("batch_team", C.c_int32), ("precond", C.c_int32), ("orth", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -236,7 +237,7 @@ def _stream(stream=None) -> int:
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
             workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
             batch_graph=False, batch_team=0, precond=PRECOND_NONE,
-            orth=ORTH_CHOL) -> OptionsC:
+            orth=ORTH_CHOL, graph=False) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -255,6 +256,7 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
     o.batch_team = int(batch_team)
     o.precond = int(precond)
     o.orth = int(orth)
+    o.graph = 1 if graph else 0
     return o
 
 
