@@ -45,6 +45,56 @@ __device__ inline void gram_factor(const double* W, int ldw, int n, double rank_
     }
 }
 
+// gram_factor for a workgroup of one wave, in LDS: W (symmetric, ld kMaxS,
+// overwritten) and F are shared.  The elimination runs column by column of U
+// with the trailing updates spread over the lanes; every entry sees the same
+// floating-point operations in the same order as in gram_factor (scaling,
+// then the subtractions U_ki U_kj for k = 0, 1, ..., then the division or the
+// square root), so F is identical on its leading rank x rank part and on
+// column `rank` above the diagonal.  All lanes must call it.
+__device__ inline void gram_factor_wave(double* W, int n, double rank_tol, GramFactor* F) {
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        F->n = n;
+        F->rank = n;
+    }
+    for (int i = lane; i < n; i += 64) {
+        const double d = W[i + i * kMaxS];
+        F->sc[i] = d > 0.0 ? rsqrt(d) : 0.0;
+    }
+    __syncthreads();
+    // scaled upper triangle
+    for (int idx = lane; idx < n * n; idx += 64) {
+        const int i = idx % n, j = idx / n;
+        if (i <= j) W[i + j * kMaxS] = W[i + j * kMaxS] * F->sc[i] * F->sc[j];
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // pivot k (uniform decision)
+        if (F->sc[k] == 0.0 || !(W[k + k * kMaxS] > rank_tol)) {
+            __syncthreads();
+            if (lane == 0) F->rank = k;
+            return;
+        }
+        const double piv = sqrt(W[k + k * kMaxS]);
+        for (int j = k + 1 + lane; j < n; j += 64) F->U[k + j * kMaxS] = W[k + j * kMaxS] / piv;
+        for (int i = k + 1 + lane; i < n; i += 64) F->U[i + k * kMaxS] = 0.0;
+        if (lane == 0) F->U[k + k * kMaxS] = piv;
+        __syncthreads();
+        // trailing update of the upper triangle: entries (i, j), k < i <= j
+        const int m = n - 1 - k;
+        for (int idx = lane; idx < m * m; idx += 64) {
+            const int i = k + 1 + idx % m, j = k + 1 + idx / m;
+            if (i <= j) {
+                double v = W[i + j * kMaxS];
+                v -= F->U[k + i * kMaxS] * F->U[k + j * kMaxS];
+                W[i + j * kMaxS] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // z = W^{-1} b on the leading rank x rank part; z[rank..n) = 0.  b, z may alias.
 __device__ inline void gram_solve(const GramFactor& F, const double* b, double* z) {
     double u[kMaxS];

@@ -173,7 +173,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_proj(GmArrays a) {
 // Gout is the Gram of the stored columns [w_hat_k, y_1..y_s] (s+1 square).
 // A rank-deficient W_k (pivot below rank_tol) truncates the block to its
 // leading q columns; column q then plays the role of Yhat_s with nu = 0.
-// Factor work happens in LDS (one thread), then the factor is copied out.
+// The factor is computed in LDS by the wave, the solves by one thread, then
+// the factor is copied out.
 __global__ __launch_bounds__(64) void k_gm_block(GmArrays a) {
     __shared__ GramFactor F;
     __shared__ double W[kMaxS * kMaxS];
@@ -186,9 +187,10 @@ __global__ __launch_bounds__(64) void k_gm_block(GmArrays a) {
         W[p + q * kMaxS] = a.Gout[p * s1 + q] * (p == 0 ? d0 : 1.0) * (q == 0 ? d0 : 1.0);
     }
     __syncthreads();
+    gram_factor_wave(W, s, st->rank_tol, &F);  // W is overwritten
+    __syncthreads();
     if (threadIdx.x == 0) {
         st->yhat2 = a.Gout[s * s1 + s];
-        gram_factor(W, kMaxS, s, st->rank_tol, &F);
         const int q = F.rank;
         if (q == s) {
             double h[kMaxS], g[kMaxS];
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(64) void k_gm_block(GmArrays a) {
             st->skip_n4b = 0;
         } else if (q > 0) {
             double h[kMaxS], g[kMaxS];
-            for (int p = 0; p < q; ++p) h[p] = W[p + q * kMaxS];
+            for (int p = 0; p < q; ++p) h[p] = a.Gout[p * s1 + q] * (p == 0 ? d0 : 1.0);
             gram_solve_leading(F, q, h, g);
             for (int p = 0; p < s; ++p) st->g[p] = p < q ? g[p] : 0.0;
             st->skip_n4b = 1;

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kThreads) void k_om_start(OmArrays a, const double*
 
 // Scalar1: factor W_i (into ring slot), a_i = W_i^{-1} m_i.
 // Gout: s x (s+1) = AP_i^T [AP_i | r].
-__global__ void k_om_step1(OmArrays a, int slot) {
+__global__ __launch_bounds__(64) void k_om_step1(OmArrays a, int slot) {
     // the factorisation works on LDS copies (read-after-write chains through
     // global memory would wait a memory round trip per step); the factor is
     // copied out at the end
@@ -116,10 +116,11 @@ __global__ void k_om_step1(OmArrays a, int slot) {
         W[p + q * kMaxS] = a.Gout[p * (s + 1) + q];
     }
     __syncthreads();
+    gram_factor_wave(W, s, st->rank_tol, &F);  // the wave factors; W is overwritten
+    __syncthreads();
     if (threadIdx.x == 0) {
         double m[kMaxS];
         for (int q = 0; q < s; ++q) m[q] = a.Gout[q * (s + 1) + s];
-        gram_factor(W, kMaxS, s, st->rank_tol, &F);
         if (F.rank == 0) {
             st->err = SSTEP_ERR_BREAKDOWN;
             st->done = 1;
