@@ -24,6 +24,7 @@ _LIB = os.environ.get("SSTEP_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 MONOMIAL = 0
 CHEBYSHEV = 1
+NEWTON = 2
 
 OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOMEM = 0, 1, -1, -2, -3, -5
 
@@ -90,6 +91,8 @@ def _load():
     lib.orc_somin.restype = C.c_int
     lib.orc_somin.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, rp,
                               dp, C.c_int, C.POINTER(_OminDump)]
+    lib.orc_newton_shifts.restype = None
+    lib.orc_newton_shifts.argtypes = [C.c_int, C.c_double, C.c_double, dp]
     lib.orc_somin_ex.restype = C.c_int
     lib.orc_somin_ex.argtypes = [sp, dp, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
                                  C.c_int, rp, dp, C.c_int, C.POINTER(_OminDump)]
@@ -173,11 +176,18 @@ def cheb_interval(A: Operator):
     return c.value, d.value
 
 
+def newton_shifts(s: int, centre: float, half_width: float) -> np.ndarray:
+    """Leja-ordered Chebyshev points of the interval: the Newton-basis shifts."""
+    th = np.empty(s)
+    _load().orc_newton_shifts(s, centre, half_width, _dp(th))
+    return th
+
+
 def mpk(A: Operator, y0: np.ndarray, s: int, basis: int = MONOMIAL) -> np.ndarray:
     """Matrix powers [y_0 .. y_s] of y0 (Sec. 3-4), shape (s+1, N)."""
     lib = _load()
     sg = sigma(A)
-    cc, cd = cheb_interval(A) if basis == CHEBYSHEV else (0.0, 1.0)
+    cc, cd = cheb_interval(A) if basis != MONOMIAL else (0.0, 1.0)
     Y = np.empty((s + 1, A.N))
     y0 = np.ascontiguousarray(y0, dtype=np.float64)
     lib.orc_mpk(A.ref, _dp(y0), s, basis, sg, cc, cd, _dp(Y))

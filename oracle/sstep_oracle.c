@@ -237,21 +237,50 @@ void orc_cheb_interval(const orc_stencil *A, double *centre, double *half_width)
     if (!(*half_width > 0.0)) *half_width = fabs(*centre) > 0.0 ? fabs(*centre) : 1.0;
 }
 
+void orc_newton_shifts(int s, double cc, double cd, double *th)
+{
+    double pts[16];
+    int used[16] = {0};
+    for (int k = 0; k < s; ++k) pts[k] = cc + cd * cos((2.0 * k + 1.0) * ORC_PI / (2.0 * s));
+    for (int n = 0; n < s; ++n) {
+        int best = -1;
+        double bv = -1.0;
+        for (int k = 0; k < s; ++k) {
+            if (used[k]) continue;
+            double v;
+            if (n == 0) {
+                v = fabs(pts[k]);
+            } else {
+                v = 1.0;
+                for (int j = 0; j < n; ++j) v *= fabs(pts[k] - th[j]);
+            }
+            if (v > bv) { bv = v; best = k; }
+        }
+        used[best] = 1;
+        th[n] = pts[best];
+    }
+}
+
 /* Matrix powers of one vector (Sec. 3-4: the s directions r, Ar, ..., A^s r).
  * Y is [(s+1)][N]; Y[0] = y0.
  *   monomial : y_j = A y_{j-1} / sigma
  *   Chebyshev: y_1 = (A - c) y_0 / d,  y_{j+1} = 2 (A - c) y_j / d - y_{j-1}
- * Both give span{y_0..y_j} = span{y_0, A y_0, ..., A^j y_0}. */
+ *   Newton   : y_{j+1} = (A - th_j) y_j / d, th the Leja-ordered shifts
+ * All give span{y_0..y_j} = span{y_0, A y_0, ..., A^j y_0}. */
 void orc_mpk(const orc_stencil *A, const double *y0, int s, int basis, double sigma,
              double cc, double cd, double *Y)
 {
     const long long N = orc_size(A);
+    double th[16];
+    if (basis == ORC_BASIS_NEWTON) orc_newton_shifts(s, cc, cd, th);
     if (Y != y0) memcpy(Y, y0, sizeof(double) * N);
     for (int j = 1; j <= s; ++j) {
         double *yj = Y + (long long)j * N;
         const double *yp = Y + (long long)(j - 1) * N;
         orc_apply(A, yp, yj);
-        if (basis == ORC_BASIS_CHEBYSHEV) {
+        if (basis == ORC_BASIS_NEWTON) {
+            for (long long p = 0; p < N; ++p) yj[p] = (yj[p] - th[j - 1] * yp[p]) / cd;
+        } else if (basis == ORC_BASIS_CHEBYSHEV) {
             if (j == 1) {
                 for (long long p = 0; p < N; ++p) yj[p] = (yj[p] - cc * yp[p]) / cd;
             } else {
@@ -270,8 +299,13 @@ void orc_mpk(const orc_stencil *A, const double *y0, int s, int basis, double si
 static void basis_change(int s, int basis, double sigma, double cc, double cd, double *B)
 {
     memset(B, 0, sizeof(double) * (s + 1) * s);
+    double th[16];
+    if (basis == ORC_BASIS_NEWTON) orc_newton_shifts(s, cc, cd, th);
     for (int j = 0; j < s; ++j) {
-        if (basis == ORC_BASIS_CHEBYSHEV) {
+        if (basis == ORC_BASIS_NEWTON) {
+            B[j + j * (s + 1)] = th[j];
+            B[(j + 1) + j * (s + 1)] = cd;
+        } else if (basis == ORC_BASIS_CHEBYSHEV) {
             if (j == 0) {
                 B[0 + 0 * (s + 1)] = cc;
                 B[1 + 0 * (s + 1)] = cd;
@@ -563,7 +597,7 @@ int orc_somin_ex(const orc_stencil *A, const double *f, double *x, int s, int k,
     if (max_iters <= 0) max_iters = 100000;
     const double sigma = orc_sigma(A);
     double cc = 0.0, cd = 1.0;
-    if (basis == ORC_BASIS_CHEBYSHEV) orc_cheb_interval(A, &cc, &cd);
+    if (basis != ORC_BASIS_MONOMIAL) orc_cheb_interval(A, &cc, &cd);
     double B[17 * 16];
     basis_change(s, basis, sigma, cc, cd, B);
 
@@ -922,7 +956,7 @@ int orc_sgmres(const orc_stencil *A, const double *f, double *x, int s, int m, d
     if (max_blocks <= 0) max_blocks = 1000 * m;
     const double sigma = orc_sigma(A);
     double cc = 0.0, cd = 1.0;
-    if (basis == ORC_BASIS_CHEBYSHEV) orc_cheb_interval(A, &cc, &cd);
+    if (basis != ORC_BASIS_MONOMIAL) orc_cheb_interval(A, &cc, &cd);
     double Bc[17 * 16];
     basis_change(s, basis, sigma, cc, cd, Bc);
     double *r = malloc(sizeof(double) * N);

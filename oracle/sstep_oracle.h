@@ -33,7 +33,14 @@ typedef struct {
 } orc_stencil;
 
 /* basis of the s-dimensional Krylov block */
-enum { ORC_BASIS_MONOMIAL = 0, ORC_BASIS_CHEBYSHEV = 1 };
+enum { ORC_BASIS_MONOMIAL = 0, ORC_BASIS_CHEBYSHEV = 1, ORC_BASIS_NEWTON = 2 };
+
+/* Shifts of the Newton basis (the larger-s stabilisation of Sec. 3-4): the s
+ * Chebyshev points centre + half_width cos((2k+1) pi / (2s)), k = 0..s-1, of
+ * the spectral interval, in Leja order (first the point of largest modulus,
+ * then each time the point maximising the product of distances to those
+ * already taken; ties to the smaller k).  th: [s]. */
+void orc_newton_shifts(int s, double centre, double half_width, double *th);
 
 /* status codes (same meaning as the GPU library's, independently defined) */
 enum {
