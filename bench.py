@@ -282,14 +282,19 @@ def bench_mixed3d(args):
     f = torch.empty_like(xt)
     S.stencil_apply(A, xt, f)
     tol = 1e-10
-    wsb = max(S.workspace_bytes(A, S.METHOD_GMRES, 8, args.m),
+    wsb = max(S.workspace_bytes(A, S.METHOD_GMRES, 12, args.m),
               S.workspace_bytes(A, S.METHOD_GMRES, 12, args.m, S.MIXED))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     x = torch.zeros_like(xt)
     res = {}
     for name, s, prec, basis in [("fp64_s8", 8, S.FP64, S.MONOMIAL), ("mixed_s4", 4, S.MIXED, S.MONOMIAL),
                                  ("mixed_s8", 8, S.MIXED, S.CHEBYSHEV),
-                                 ("mixed_s12", 12, S.MIXED, S.CHEBYSHEV)]:
+                                 ("mixed_s12", 12, S.MIXED, S.CHEBYSHEV),
+                                 # larger s in FP64: the three bases side by side
+                                 ("fp64_s12_monomial", 12, S.FP64, S.MONOMIAL),
+                                 ("fp64_s12_chebyshev", 12, S.FP64, S.CHEBYSHEV),
+                                 ("fp64_s12_newton", 12, S.FP64, S.NEWTON),
+                                 ("mixed_s12_newton", 12, S.MIXED, S.NEWTON)]:
         infos = []
         for rep in range(args.warmup + args.steps):
             x.zero_()
@@ -305,7 +310,8 @@ def bench_mixed3d(args):
         xerr = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
         res[name] = {"s": t, "blocks": info.iters, "cycles": info.cycles, "status": info.status,
                      "rel_resid": info.rel_resid, "x_err_vs_true": xerr,
-                     "basis": "chebyshev" if basis == S.CHEBYSHEV else "monomial",
+                     "basis": {S.MONOMIAL: "monomial", S.CHEBYSHEV: "chebyshev",
+                               S.NEWTON: "newton"}[basis],
                      "kernels": _classes(S, [i for _, i in infos], len(infos))}
         print(f"# {name}: {t:.3f} s blocks={info.iters} cycles={info.cycles} rel_resid={info.rel_resid:.2e}"
               f" x_err={xerr:.2e}", file=sys.stderr, flush=True)
@@ -314,7 +320,8 @@ def bench_mixed3d(args):
     _line("mixed-precision s-step GMRES time to 1e-10 rel. resid, 7-pt 256^3", v, "s", False, v * 1e3,
           args, "f32+f64",
           f"3-D 7-pt convection-diffusion {args.n}^3 gamma=50, s-step GMRES(m={args.m}), FP32 basis, "
-          f"FP64 Gram/LS/refinement, tol 1e-10 (s=8 headline; s=4, 12 and FP64 s=8 alongside)",
+          f"FP64 Gram/LS/refinement, tol 1e-10 (s=8 headline; s=4, 12, FP64 s=8 and FP64 s=12 "
+          f"with monomial / Chebyshev / Newton bases alongside)",
           {"results": res, "speedup_vs_fp64": res["fp64_s8"]["s"] / v,
            "roofline": {"bound": "hbm", "kernel": "update", "achieved": upd, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": upd / HBM_PEAK_GBS, "traffic": None}})

@@ -62,7 +62,12 @@ typedef struct {
     const double *coef;         /* optional DEVICE [7][N]                          */
 } sstep_stencil;
 
-enum { SSTEP_BASIS_MONOMIAL = 0, SSTEP_BASIS_CHEBYSHEV = 1 };
+/* Krylov basis of the matrix-powers kernel (all span the same space):
+ * monomial y_j = A y_{j-1} / sigma; Chebyshev three-term recurrence on the
+ * spectral interval [c - d, c + d]; Newton y_j = (A - th_{j-1}) y_{j-1} / d
+ * with th the s Chebyshev points of that interval in Leja order (the
+ * larger-s stabilisation; s-Omin and s-GMRES, not the batched solver). */
+enum { SSTEP_BASIS_MONOMIAL = 0, SSTEP_BASIS_CHEBYSHEV = 1, SSTEP_BASIS_NEWTON = 2 };
 enum { SSTEP_FP64 = 0, SSTEP_MIXED = 1 };
 enum { SSTEP_METHOD_OMIN = 0, SSTEP_METHOD_GMRES = 1 };
 enum { SSTEP_PRECOND_NONE = 0, SSTEP_PRECOND_ILU0 = 1 };
@@ -75,8 +80,9 @@ typedef struct {
                              matrix powers and block updates in FP32; Gram matrices,
                              small solves, Hessenberg least squares, x and the restart
                              residual in FP64 (iterative refinement by restarts)           */
-    int32_t basis;        /* SSTEP_BASIS_MONOMIAL (y_j = A y_{j-1} / sigma) or
-                             SSTEP_BASIS_CHEBYSHEV (same Krylov span, better conditioned)  */
+    int32_t basis;        /* SSTEP_BASIS_MONOMIAL (y_j = A y_{j-1} / sigma),
+                             SSTEP_BASIS_CHEBYSHEV or SSTEP_BASIS_NEWTON (same Krylov
+                             span, better conditioned)                                    */
     int32_t profile;      /* 1: time each kernel class with HIP events into info           */
     double sigma;         /* power scaling; 0 = smallest power of two >= Gershgorin bound */
     double inner_tol;     /* SSTEP_MIXED: a cycle stops once its least-squares residual

@@ -196,7 +196,8 @@ int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s,
     if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
         s > kMaxS || m < 1 || (long long)m * s > 2048 ||
         !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
-        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
+        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV &&
+         basis != SSTEP_BASIS_NEWTON) ||
         (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0) ||
                  opt->orth != SSTEP_ORTH_CHOL)) ||
         !precond_ok(A, opt, prec, basis)) {
@@ -223,7 +224,9 @@ int sstep_omin_solve(const sstep_stencil* A, const double* f, double* x, int s, 
     const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
     if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
         s > kMaxS || k < 1 || k > 64 || !(tol >= 0.0) ||
-        prec != SSTEP_FP64 || (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV) ||
+        prec != SSTEP_FP64 ||
+        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV &&
+         basis != SSTEP_BASIS_NEWTON) ||
         (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) ||
                  (opt->orth != SSTEP_ORTH_CHOL && opt->orth != SSTEP_ORTH_MGS))) ||
         !precond_ok(A, opt, prec, basis)) {

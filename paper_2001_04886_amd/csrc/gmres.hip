@@ -542,7 +542,8 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
     double* scratch = reinterpret_cast<double*>(ws + L.off_scratch);
     GmState* dst = a.st;
 
-    const OpParams P = op_params(Ast, opt.sigma, c.st, scratch);
+    OpParams P = op_params(Ast, opt.sigma, c.st, scratch);
+    if (opt.basis == SSTEP_BASIS_NEWTON) newton_shifts(s, P.cc, P.cd, P.th);
     // host-initialised parameters
     GmState h;
     std::memset(&h, 0, sizeof(h));

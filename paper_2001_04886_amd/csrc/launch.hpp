@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/sstep.h"
+#include "dense.hpp"
 #include "gram_self.hpp"
 #include "kernels.hpp"
 #include "mpk.hpp"
@@ -183,7 +184,35 @@ static __global__ __launch_bounds__(kThreads) void k_coef_bounds(StencilView A,
 
 struct OpParams {
     double sigma, cc, cd;
+    double th[kMaxS];  // Newton-basis shifts (SSTEP_BASIS_NEWTON)
 };
+
+// Newton-basis shifts: the s Chebyshev points cc + cd cos((2k+1) pi / (2s)) of
+// the spectral interval in Leja order -- first the point of largest modulus,
+// then each time the one maximising the product of distances to the points
+// already taken (ties to the smaller k).
+inline void newton_shifts(int s, double cc, double cd, double* th) {
+    double pts[kMaxS];
+    bool used[kMaxS] = {};
+    for (int k = 0; k < s; ++k) pts[k] = cc + cd * std::cos((2.0 * k + 1.0) * M_PI / (2.0 * s));
+    for (int n = 0; n < s; ++n) {
+        int best = -1;
+        double bv = -1.0;
+        for (int k = 0; k < s; ++k) {
+            if (used[k]) continue;
+            double v = 1.0;
+            if (n == 0) v = std::fabs(pts[k]);
+            else
+                for (int j = 0; j < n; ++j) v *= std::fabs(pts[k] - th[j]);
+            if (v > bv) {
+                bv = v;
+                best = k;
+            }
+        }
+        used[best] = true;
+        th[n] = pts[best];
+    }
+}
 
 // sigma: smallest power of two >= max_p sum_q |a_pq| (exact scaling);
 // Chebyshev interval: for constant coefficients the spectrum of the symmetric
@@ -228,7 +257,10 @@ inline OpParams op_params(const sstep_stencil& A, double sigma_opt, hipStream_t 
 inline void basis_matrix(int s, int basis, const OpParams& P, double* B) {
     std::memset(B, 0, sizeof(double) * (s + 1) * s);
     for (int j = 0; j < s; ++j) {
-        if (basis == SSTEP_BASIS_CHEBYSHEV) {
+        if (basis == SSTEP_BASIS_NEWTON) {  // A y_j = cd y_{j+1} + th_j y_j
+            B[j + j * (s + 1)] = P.th[j];
+            B[(j + 1) + j * (s + 1)] = P.cd;
+        } else if (basis == SSTEP_BASIS_CHEBYSHEV) {
             if (j == 0) {
                 B[0] = P.cc;
                 B[1] = P.cd;
@@ -354,7 +386,11 @@ inline void mpk_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T
 // lev = 1..s: y_lev = alpha A y_{lev-1} + beta y_{lev-1} + gam y_{lev-2}.
 inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, double* b,
                             double* g) {
-    if (basis == SSTEP_BASIS_CHEBYSHEV) {
+    if (basis == SSTEP_BASIS_NEWTON) {  // y_lev = (A - th_{lev-1}) y_{lev-1} / cd
+        *a = 1.0 / P.cd;
+        *b = -P.th[lev - 1] / P.cd;
+        *g = 0.0;
+    } else if (basis == SSTEP_BASIS_CHEBYSHEV) {
         *a = (lev == 1 ? 1.0 : 2.0) / P.cd;
         *b = -(lev == 1 ? 1.0 : 2.0) * P.cc / P.cd;
         *g = lev == 1 ? 0.0 : -1.0;

@@ -291,7 +291,8 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
     OmState* dst = a.st;
     const int* done = &dst->done;
 
-    const OpParams P = op_params(Ast, opt.sigma, c.st, scratch);
+    OpParams P = op_params(Ast, opt.sigma, c.st, scratch);
+    if (opt.basis == SSTEP_BASIS_NEWTON) newton_shifts(s, P.cc, P.cd, P.th);
     const int max_iters = opt.max_iters > 0 ? opt.max_iters : 10000;
     OmState h;
     std::memset(&h, 0, sizeof(h));

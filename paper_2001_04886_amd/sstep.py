@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsstep.so")
 
 OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_HIP, ERR_NOMEM = 0, 1, -1, -2, -3, -4, -5
-MONOMIAL, CHEBYSHEV = 0, 1
+MONOMIAL, CHEBYSHEV, NEWTON = 0, 1, 2
 FP64, MIXED = 0, 1
 METHOD_OMIN, METHOD_GMRES = 0, 1
 PRECOND_NONE, PRECOND_ILU0 = 0, 1
