@@ -214,7 +214,9 @@ size_t sstep_precond_workspace_bytes(const sstep_stencil *A, int precond);
 int sstep_ilu0_factor(const sstep_stencil *A, double *d, void *stream);
 
 /* z = M^{-1} r (forward then backward sweep).  d as written by
- * sstep_ilu0_factor; r, z : DEVICE [N], z must not alias r or d. */
+ * sstep_ilu0_factor; r, z : DEVICE [N], z must not alias r or d.  Allocates
+ * (stream-ordered) and frees a scratch buffer for the sweep layout of d and
+ * the coefficients on every call; the solvers keep theirs in the workspace. */
 int sstep_ilu0_solve(const sstep_stencil *A, const double *d, const double *r, double *z,
                      void *stream);
 
