@@ -553,7 +553,7 @@ inline void gram_go(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, lon
 template <typename T>
 inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1, long long ldz1,
                         int nz1, const T* Z2, long long ldz2, int nz2, long long N, double* part,
-                        double* G, const int* skip, int cls = SSTEP_K_GRAM) {
+                        double* G, const int* skip, int cls = SSTEP_K_GRAM, bool reduce = true) {
     const int nz = nz1 + nz2;
     int KZ, CA, nct, nchunk;
     long long chunk;
@@ -572,8 +572,9 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
         else
             hipLaunchKernelGGL((k_gram_self<T, 9>), g, b, 0, c.st, X, ldx, ncx, N, chunk, KZ, part, skip);
         SSTEP_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_gram_reduce, dim3((ncx * nz + 63) / 64), dim3(kThreads), 0, c.st, part,
-                           nchunk, ncx, KZ, nz, G, skip);
+        if (reduce)
+            hipLaunchKernelGGL(k_gram_reduce, dim3((ncx * nz + 63) / 64), dim3(kThreads), 0, c.st,
+                               part, nchunk, ncx, KZ, nz, G, skip);
         SSTEP_HIP(hipGetLastError());
         c.end();
         return;
@@ -600,8 +601,9 @@ inline void launch_gram(Ctx& c, const T* X, long long ldx, int ncx, const T* Z1,
 #undef SSTEP_GRAM_CASE
     SSTEP_HIP(hipGetLastError());
     const int nout = ncx * nz;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(kThreads), 0, c.st, part, nchunk,
-                       ncx, KZ, nz, G, skip);
+    if (reduce)
+        hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(kThreads), 0, c.st, part,
+                           nchunk, ncx, KZ, nz, G, skip);
     SSTEP_HIP(hipGetLastError());
     c.end();
 }

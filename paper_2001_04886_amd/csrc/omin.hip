@@ -21,9 +21,10 @@
 //   update   P_{i+1} = R + sum P_j B_j;  AP_{i+1} = AR + sum AP_j B_j (8-9)
 // With orth = SSTEP_ORTH_MGS every new block (P, AP) is then made
 // A^T A-orthogonal by modified Gram-Schmidt on the device (the larger-s
-// variant of Sec. 3): for q = 0..s-1 one Gram of AP_q against AP_q..AP_{s-1},
-// one scalar kernel for the coefficients and the dependence test, and one
-// update each of P_q..P_{s-1} and AP_q..AP_{s-1}.  W of the block is then
+// variant of Sec. 3): for q = 0..s-1 the first stage of a Gram of AP_q
+// against AP_q..AP_{s-1}, one scalar kernel that sums its partials and forms
+// the coefficients and the dependence test, and one pass over P_q..P_{s-1}
+// and AP_q..AP_{s-1}.  W of the block is then
 // diagonal, and the Cholesky of Scalar1 / Scalar2 reduces to it.
 #include <hip/hip_runtime.h>
 
@@ -203,16 +204,27 @@ __global__ __launch_bounds__(kThreads) void k_om_step2(OmArrays a, int nfill) {
     }
 }
 
-// MGS step q on the block whose Gram row G = AP_q^T [AP_q .. AP_{s-1}] is in
-// Gout: w = G[0] is the squared length of AP_q after its components along
-// AP_0..AP_{q-1} were removed, n0 = w + (removed) its length before.  Column
-// q is kept if w > rank_tol * n0 (else it is numerically dependent and set to
-// zero); the coefficient row for columns q..s-1 is [keep - 1, -G[l]/w ...].
-__global__ __launch_bounds__(64) void k_om_mgs(OmArrays a, int q) {
+// MGS step q.  The Gram row G = AP_q^T [AP_q .. AP_{s-1}] is summed here from
+// the partials of the Gram's first stage (fixed order: lane-strided chunks,
+// then a wave sum).  w = G[0] is the squared length of AP_q after its
+// components along AP_0..AP_{q-1} were removed, n0 = w + (removed) its length
+// before.  Column q is kept if w > rank_tol * n0 (else it is numerically
+// dependent and set to zero); the coefficient row for columns q..s-1 is
+// [keep - 1, -G[l]/w ...].
+__global__ __launch_bounds__(64) void k_om_mgs(OmArrays a, int q, const double* __restrict__ part,
+                                               int nchunk, int KZ) {
+    __shared__ double G[kMaxS];
     OmState* st = a.st;
-    if (st->done || threadIdx.x != 0) return;
+    if (st->done) return;
     const int s = st->s;
-    const double* G = a.Gout;
+    for (int j = 0; j < s - q; ++j) {
+        double v = 0.0;
+        for (int ch = threadIdx.x; ch < nchunk; ch += 64) v += part[(long long)ch * KZ + j];
+        v = wave_sum(v);
+        if (threadIdx.x == 0) G[j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     if (q == 0)
         for (int l = 0; l < s; ++l) st->mgs_removed[l] = 0.0;
     const double w = G[0];
@@ -224,6 +236,24 @@ __global__ __launch_bounds__(64) void k_om_mgs(OmArrays a, int q) {
         const double c = keep ? g / w : 0.0;
         st->mgs_row[l - q] = -c;
         st->mgs_removed[l] += c * g;
+    }
+}
+
+// MGS step q applied to both blocks: column q kept or zeroed, columns q+1..
+// minus their coefficient times column q, for P and AP in one pass.
+__global__ __launch_bounds__(kThreads) void k_om_mgs_apply(OmArrays a, long long N, double* P,
+                                                           double* AP, long long ld, int ncol) {
+    const OmState* st = a.st;
+    if (st->done) return;
+    const long long p = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= N) return;
+    const double* row = st->mgs_row;
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+        double* X = blk ? AP : P;
+        const double xq = X[p];
+        X[p] = fma(row[0], xq, xq);
+        for (int l = 1; l < ncol; ++l) X[l * ld + p] = fma(row[l], xq, X[l * ld + p]);
     }
 }
 
@@ -346,16 +376,19 @@ int omin_solve_impl(Ctx& c, const sstep_stencil& Ast, const double* f, double* x
         for (int q = 0; q < s; ++q) {
             double* Pq = Pb + (long long)q * ld;
             double* APq = APb + (long long)q * ld;
+            // first stage of the Gram only: k_om_mgs sums the partials itself
             launch_gram<double>(c, APq, ld, 1, APq, ld, s - q, (const double*)nullptr, 0, 0, N,
-                                gpart, a.Gout, done, SSTEP_K_VEC);
-            scalar(k_om_mgs, 64, q);
-            // columns q..s-1 += column q x row (column q itself: kept or zeroed)
-            launch_update<double, double, double, double, false>(
-                c, N, Pq, ld, Pq, ld, 1, nullptr, dst->mgs_row, Pq, ld, s - q, nullptr, done,
-                (2.0 * (s - q) + 1) * vb, SSTEP_K_VEC);
-            launch_update<double, double, double, double, false>(
-                c, N, APq, ld, APq, ld, 1, nullptr, dst->mgs_row, APq, ld, s - q, nullptr, done,
-                (2.0 * (s - q) + 1) * vb, SSTEP_K_VEC);
+                                gpart, a.Gout, done, SSTEP_K_VEC, /*reduce=*/false);
+            int KZ, CA, nct, nchunk;
+            long long chunk;
+            gram_geometry(N, 1, s - q, &KZ, &CA, &nct, &nchunk, &chunk);
+            scalar(k_om_mgs, 64, q, (const double*)gpart, nchunk, KZ);
+            // columns q..s-1 of P and AP += column q x row (column q: kept or zeroed)
+            c.begin(SSTEP_K_VEC, 2.0 * (2.0 * (s - q)) * vb);
+            hipLaunchKernelGGL(k_om_mgs_apply, dim3((unsigned)((N + kThreads - 1) / kThreads)),
+                               dim3(kThreads), 0, c.st, a, N, Pq, APq, ld, s - q);
+            SSTEP_HIP(hipGetLastError());
+            c.end();
         }
     };
     // R_0, AR_0 from the current r (Y[:,0]) into slot 0
