@@ -228,9 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_nu(GmArrays a, const double* __
     GmState* st = a.st;
     if (st->done) return;
     const int s = st->s, q = a.Wf[st->kb].rank;
-    double acc = 0.0;
-    if (q == s)
-        for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
+    const double acc = q == s ? strided_partial_sum(part, npart) : 0.0;
     double v[1] = {acc}, o[1];
     block_sum<1>(v, lds, o);
     if (threadIdx.x == 0) {

@@ -63,6 +63,20 @@ struct LaunchRec {
     int ev;
 };
 
+// Sum of this thread's share of n partial sums (threads stride by kThreads),
+// eight independent accumulators so that eight loads are in flight at once,
+// combined in a fixed order.
+__device__ __forceinline__ double strided_partial_sum(const double* __restrict__ part, int n) {
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int i = threadIdx.x;
+    for (; i + 7 * kThreads < n; i += 8 * kThreads) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += part[i + u * kThreads];
+    }
+    for (; i < n; i += kThreads) acc[0] += part[i];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 // ILU(0) right preconditioner of a 2-D five-point operator (Sec. 5): pivots,
 // their reciprocals, and a scratch vector for M^{-1} of one vector.
 struct Ilu0 {

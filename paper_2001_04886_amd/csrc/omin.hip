@@ -147,9 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_om_check(OmArrays a, const double*
     __shared__ double lds[4];
     OmState* st = a.st;
     if (st->done) return;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < npart; i += kThreads) acc += part[i];
-    double v[1] = {acc}, o[1];
+    double v[1] = {strided_partial_sum(part, npart)}, o[1];
     block_sum<1>(v, lds, o);
     if (threadIdx.x == 0) {
         const double rn = sqrt(o[0]);
