@@ -1,0 +1,246 @@
+"""GPU parity at the benchmarked sizes, in the launch configurations the
+benchmark times.
+
+Kernels at N = 256^3 = 2^24: the 7-point stencil and the s = 8 matrix powers
+are compared element by element with the FP64 oracle (which finishes them in
+seconds); the block Gram and block update at the widest shape of an
+s-GMRES(m=40, s=8) cycle (312 basis columns against an 8-column block) are
+compared on sampled outputs that numpy recomputes one by one from copies of
+the inputs.
+
+Solvers at full size: the oracle cannot run these solves in seconds, so each
+is checked by a property that holds at any size: the true residual
+||f - A x|| / ||f||, recomputed on the CPU by the oracle's FP64 operator from
+the returned x, is within the requested tolerance (eq. (1) stopping test) and
+agrees with the residual the library reports.  Right-hand sides are built by
+the oracle operator as well (f = A x_true), so no input comes from the HIP
+path."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2001_04886_amd import problems as PB
+from paper_2001_04886_amd import sstep as S
+from paper_2001_04886_amd import tune as TU
+from helpers import operator
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+U = 2.0 ** -53          # unit roundoff of FP64
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def cube():
+    """The 256^3 7-point problem, gamma = 50, x_true ~ U(-1, 1) seed 0."""
+    prob = PB.cube_3d(256, seed=0, gamma=50.0)
+    Ao = operator(prob)
+    xt = prob.x_true()
+    f = O.apply(Ao, xt)
+    return prob, Ao, S.Stencil.from_problem(prob), f
+
+
+def release():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def true_residual(Ao, f, x):
+    return float(np.linalg.norm(f - O.apply(Ao, x)) / np.linalg.norm(f))
+
+
+# --------------------------------------------------------------------------
+# kernels at 256^3
+# --------------------------------------------------------------------------
+
+def test_stencil_apply_full(cube):
+    prob, Ao, Ag, f = cube
+    x = PB.x_true(11, prob.N)
+    y = torch.empty(prob.N, dtype=torch.float64, device=DEV)
+    S.stencil_apply(Ag, dev(x), y)
+    yo = O.apply(Ao, x)
+    assert np.abs(host(y) - yo).max() <= 4e-16 * np.abs(prob.c).sum() * 8
+    release()
+
+
+@pytest.mark.parametrize("basis", [S.MONOMIAL, S.CHEBYSHEV])
+def test_matrix_powers_full(cube, basis):
+    # s = 8 levels from one start vector, the whole output against the oracle
+    prob, Ao, Ag, f = cube
+    s, scale = 8, 0.37
+    w = PB.x_true(13, prob.N)
+    Y = torch.zeros((s + 1, prob.N), dtype=torch.float64, device=DEV)
+    Y[0] = dev(w)
+    cc, cd = O.cheb_interval(Ao)
+    S.kernel_mpk(Ag, Y, s, basis, scale, O.sigma(Ao), cc, cd)
+    Yg = host(Y)
+    del Y
+    Yo = O.mpk(Ao, w * scale, s, basis)
+    for j in range(1, s + 1):
+        assert rel(Yg[j], Yo[j]) < 1e-13 * (j + 1), j
+    release()
+
+
+def _gen(shape, seed):
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    return torch.randn(shape, dtype=torch.float64, device=DEV, generator=g)
+
+
+def test_block_gram_full_sampled():
+    # G = X^T Z with 312 columns against 8 (last block of an m = 40, s = 8
+    # cycle) at N = 2^24; 64 sampled entries recomputed by numpy, and the
+    # call repeated for bitwise determinism
+    N, ncx, ncz = 1 << 24, 312, 8
+    X = _gen((ncx, N), 101)
+    Z = _gen((ncz, N), 102)
+    G = host(S.kernel_gram(X, Z))
+    G2 = host(S.kernel_gram(X, Z))
+    assert np.array_equal(G, G2)
+    Zh = host(Z)
+    rows = [0, 1, 97, 150, 200, 255, 310, 311]
+    for j in rows:
+        xj = host(X[j])
+        for k in range(ncz):
+            ref = float(np.dot(xj, Zh[k]))
+            bound = 1e-15 * np.sqrt(N) * 8 * np.linalg.norm(xj) * np.linalg.norm(Zh[k])
+            assert abs(G[j, k] - ref) <= bound, (j, k)
+    del X, Z
+    release()
+
+
+def test_block_self_gram_full():
+    # X^T X of one 9-column block (s + 1 for s = 8), every entry
+    N, nc = 1 << 24, 9
+    X = _gen((nc, N), 103)
+    G = host(S.kernel_gram(X, X))
+    Xh = host(X)
+    ref = Xh @ Xh.T
+    nrm = np.linalg.norm(Xh, axis=1)
+    assert np.all(np.abs(G - ref) <= 1e-15 * np.sqrt(N) * 8 * np.outer(nrm, nrm))
+    assert np.array_equal(G, G.T)
+    del X
+    release()
+
+
+def test_block_update_full_sampled():
+    # Y[l] += sum_c X[c] M[c, l] with 312 columns into 8 at N = 2^24; 8192
+    # sampled rows (first and last tile included) recomputed by numpy within
+    # the standard rounding bound of a length-(ncx + 1) sum, counted for both
+    # sides
+    N, ncx, ncy = 1 << 24, 312, 8
+    X = _gen((ncx, N), 104)
+    Y = _gen((ncy, N), 105)
+    rng = np.random.default_rng(106)
+    Mh = rng.standard_normal((ncx, ncy)) / ncx
+    rows = np.unique(np.concatenate([np.arange(64), np.arange(N - 64, N),
+                                     rng.integers(0, N, 8192 - 128)]))
+    ri = torch.from_numpy(rows).to(DEV)
+    Xs = host(X[:, ri])
+    Y0 = host(Y[:, ri])
+    S.kernel_update(X, Y, dev(Mh))
+    Ys = host(Y[:, ri])
+    ref = Y0 + (Xs.T @ Mh).T
+    bound = 2 * (ncx + 2) * U * (np.abs(Y0) + (np.abs(Xs).T @ np.abs(Mh)).T)
+    assert np.all(np.abs(Ys - ref) <= bound)
+    del X, Y
+    release()
+
+
+# --------------------------------------------------------------------------
+# solvers at full size
+# --------------------------------------------------------------------------
+
+def test_headline_sgmres_true_residual(cube):
+    # 256^3, s-GMRES(m = 40, s = 8), FP64, monomial basis, tol 1e-8, x0 = 0
+    prob, Ao, Ag, f = cube
+    ws = S.allocate_workspace(Ag, S.METHOD_GMRES, 8, 40)
+    x = torch.zeros(prob.N, dtype=torch.float64, device=DEV)
+    info = S.gmres_solve(Ag, dev(f), x, 8, 40, 1e-8, workspace=ws, profile=True)
+    assert info.status == S.OK
+    assert info.rel_resid <= 1e-8
+    r = true_residual(Ao, f, host(x))
+    assert r <= 1e-8 * (1 + 1e-6)
+    assert abs(r - info.rel_resid) <= 1e-13
+    del ws, x
+    release()
+
+
+def test_mixed_precision_true_residual(cube):
+    # same problem, FP32 basis and updates, FP64 Gram / least squares /
+    # refinement, s = 8 Chebyshev basis, tol 1e-10 judged in FP64
+    prob, Ao, Ag, f = cube
+    ws = S.allocate_workspace(Ag, S.METHOD_GMRES, 8, 40, S.MIXED)
+    x = torch.zeros(prob.N, dtype=torch.float64, device=DEV)
+    info = S.gmres_solve(Ag, dev(f), x, 8, 40, 1e-10, precision=S.MIXED, basis=S.CHEBYSHEV,
+                         workspace=ws, profile=True)
+    assert info.status == S.OK
+    assert info.rel_resid <= 1e-10
+    r = true_residual(Ao, f, host(x))
+    assert r <= 1e-10 * (1 + 1e-4)
+    assert abs(r - info.rel_resid) <= 1e-13
+    del ws, x
+    release()
+
+
+def test_omin_4096sq_true_residual():
+    # 2-D 4096^2 5-point, gamma = 50, s-Omin(k = 8, s = 8), FP64, tol 1e-8
+    prob = PB.square_2d_large(4096, seed=0, gamma=50.0)
+    Ao = operator(prob)
+    Ag = S.Stencil.from_problem(prob)
+    f = O.apply(Ao, prob.x_true())
+    ws = S.allocate_workspace(Ag, S.METHOD_OMIN, 8, 8)
+    x = torch.zeros(prob.N, dtype=torch.float64, device=DEV)
+    info = S.omin_solve(Ag, dev(f), x, 8, 8, 1e-8, max_iters=600, workspace=ws, profile=True)
+    assert info.status == S.OK
+    r = true_residual(Ao, f, host(x))
+    assert r <= 1e-8 * (1 + 1e-6)
+    assert abs(r - info.rel_resid) <= 1e-13
+    del ws, x
+    release()
+
+
+def test_batched_512_true_residuals():
+    # 512 uneven 2-D systems (side ~ U{32..512}, gamma ~ U(0, 100)), s = 4,
+    # m = 30, tol 1e-8, one persistent launch replayed from a hipGraph, in the
+    # committed autotuned shape when there is one
+    table = PB.batched_table(512, master_seed=0)
+    probs = [PB.convdiff(2, n, g, seed=sd) for n, g, sd in table]
+    ops = [operator(p) for p in probs]
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fh = [O.apply(a, p.x_true()) for a, p in zip(ops, probs)]
+    fs = [dev(f) for f in fh]
+    xs = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
+    shape = TU.lookup(st, 4, 30)
+    threads, wpc, team = shape if shape is not None else (0, 0, 0)
+    plan = S.BatchPlan(st, fs, xs, 4, 30, 1e-8, threads=threads, wgs_per_cu=wpc, graph=True,
+                       team=team)
+    try:
+        status, infos = plan.execute()
+    finally:
+        plan.close()
+    assert status == S.OK
+    worst = 0.0
+    for a, f, x, i in zip(ops, fh, xs, infos):
+        assert i.status == S.OK
+        r = true_residual(a, f, host(x))
+        assert r <= 1e-8 * (1 + 1e-6)
+        assert abs(r - i.rel_resid) <= 1e-13
+        worst = max(worst, r)
+    assert worst > 0.0
+    release()
