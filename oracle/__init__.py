@@ -183,11 +183,16 @@ def newton_shifts(s: int, centre: float, half_width: float) -> np.ndarray:
     return th
 
 
-def mpk(A: Operator, y0: np.ndarray, s: int, basis: int = MONOMIAL) -> np.ndarray:
-    """Matrix powers [y_0 .. y_s] of y0 (Sec. 3-4), shape (s+1, N)."""
+def mpk(A: Operator, y0: np.ndarray, s: int, basis: int = MONOMIAL, params=None) -> np.ndarray:
+    """Matrix powers [y_0 .. y_s] of y0 (Sec. 3-4), shape (s+1, N).  params =
+    (sigma, centre, half_width) overrides the scaling and interval derived
+    from A (used when A is a window cut out of a larger grid)."""
     lib = _load()
-    sg = sigma(A)
-    cc, cd = cheb_interval(A) if basis != MONOMIAL else (0.0, 1.0)
+    if params is not None:
+        sg, cc, cd = (float(v) for v in params)
+    else:
+        sg = sigma(A)
+        cc, cd = cheb_interval(A) if basis != MONOMIAL else (0.0, 1.0)
     Y = np.empty((s + 1, A.N))
     y0 = np.ascontiguousarray(y0, dtype=np.float64)
     lib.orc_mpk(A.ref, _dp(y0), s, basis, sg, cc, cd, _dp(Y))

@@ -1,0 +1,226 @@
+"""GPU parity at the largest grid the library accepts (N <= 2^31 - 1 points):
+a 1290^3 7-point grid, N = 2 146 689 000, 16 GiB per FP64 vector.
+
+Checks that need no full-size CPU copy of the operands:
+* stencil apply and s = 4 matrix powers (both bases): sampled points, each
+  recomputed by the oracle on the window of the grid that the point's value
+  depends on (the grid clipped to a box of radius s around it; clipping at the
+  domain edge keeps the Dirichlet boundary exact);
+* block Gram and block update: integer-valued periodic inputs, so every
+  product and partial sum is an integer below 2^53 and both results are exact
+  in FP64 whatever the summation order; the Gram is compared bit for bit with
+  its closed-form value, the update on sampled rows;
+* one s-GMRES cycle (m = 2, s = 2): the true residual of the returned x,
+  recomputed by the oracle's FP64 operator on the CPU, equals the one the
+  library reports and lies below ||f|| (minimal residual over a space that
+  contains 0)."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2001_04886_amd import problems as PB
+from paper_2001_04886_amd import sstep as S
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+NX = 1290                        # 1290^3 <= 2^31 - 1 < 1291^3
+N = NX ** 3
+LD = (N + 63) // 64 * 64
+C = PB.convdiff_coeffs(3, NX, NX, NX, 50.0)
+
+
+def stencil():
+    return S.Stencil(3, NX, NX, NX, tuple(C), None)
+
+
+def release():
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def rand_rows(nrow, seed):
+    """(nrow, LD) float64 device tensor, U(-1, 1) in the first N entries."""
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    Y = torch.zeros((nrow, LD), dtype=torch.float64, device=DEV)
+    for r in range(nrow):
+        Y[r, :N].uniform_(-1.0, 1.0, generator=g)
+    return Y
+
+
+def sample_points(nrand, seed):
+    """Grid points (i, j, l): the eight corners, points on each face and
+    edge, and nrand random ones."""
+    rng = np.random.default_rng(seed)
+    e = [0, 1, NX // 2, NX - 2, NX - 1]
+    pts = {(i, j, l) for i in (0, NX - 1) for j in (0, NX - 1) for l in (0, NX - 1)}
+    pts |= {(a, b, c) for a in e for b in e for c in e if 0 in (a, b, c) or NX - 1 in (a, b, c)}
+    pts |= {tuple(int(v) for v in rng.integers(0, NX, 3)) for _ in range(nrand)}
+    return sorted(pts)
+
+
+def window(i, j, l, R):
+    """Index ranges of the grid clipped to the box of radius R around
+    (i, j, l), the flat indices of its points (x fastest) and the position of
+    (i, j, l) inside it."""
+    lo = [max(0, v - R) for v in (i, j, l)]
+    hi = [min(NX - 1, v + R) for v in (i, j, l)]
+    ax = [np.arange(a, b + 1, dtype=np.int64) for a, b in zip(lo, hi)]
+    flat = (ax[2][:, None, None] * NX * NX + ax[1][None, :, None] * NX + ax[0][None, None, :]).ravel()
+    dims = [len(a) for a in ax]
+    ctr = (l - lo[2]) * dims[0] * dims[1] + (j - lo[1]) * dims[0] + (i - lo[0])
+    return dims, flat, ctr
+
+
+def gather(vec, idx):
+    return vec[torch.from_numpy(idx).to(DEV)].cpu().numpy()
+
+
+def test_stencil_apply_max_grid():
+    A = stencil()
+    X = rand_rows(1, 201)
+    Y = torch.empty((1, LD), dtype=torch.float64, device=DEV)
+    S.stencil_apply(A, X[0, :N], Y[0, :N])
+    torch.cuda.synchronize()
+    pts = sample_points(2000, 202)
+    wins = [window(i, j, l, 1) for i, j, l in pts]
+    vals = gather(X[0], np.concatenate([w[1] for w in wins]))
+    got = gather(Y[0], np.array([i + NX * j + NX * NX * l for i, j, l in pts], dtype=np.int64))
+    off = 0
+    scale = np.abs(C).sum()
+    for (dims, flat, ctr), g in zip(wins, got):
+        xw = vals[off: off + len(flat)]
+        off += len(flat)
+        ref = O.apply(O.Operator(3, dims[0], dims[1], dims[2], c=C), xw)[ctr]
+        assert abs(g - ref) <= 4e-16 * scale * 8
+    del X, Y
+    release()
+
+
+@pytest.mark.parametrize("basis", [S.MONOMIAL, S.CHEBYSHEV])
+def test_matrix_powers_max_grid(basis):
+    s, scale = 4, 0.37
+    A = stencil()
+    full = O.Operator(3, NX, NX, NX, c=C)
+    sg = O.sigma(full)
+    cc, cd = O.cheb_interval(full)
+    Y = torch.zeros((s + 1, LD), dtype=torch.float64, device=DEV)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(203 + basis)
+    Y[0, :N].uniform_(-1.0, 1.0, generator=g)
+    S.kernel_mpk(A, Y, s, basis, scale, sg, cc, cd)
+    torch.cuda.synchronize()
+    pts = sample_points(150, 204)
+    wins = [window(i, j, l, s) for i, j, l in pts]
+    vals = gather(Y[0], np.concatenate([w[1] for w in wins]))
+    cidx = np.array([i + NX * j + NX * NX * l for i, j, l in pts], dtype=np.int64)
+    got = np.stack([gather(Y[k], cidx) for k in range(1, s + 1)])
+    ref = np.empty_like(got)
+    off = 0
+    for n, (dims, flat, ctr) in enumerate(wins):
+        yw = vals[off: off + len(flat)] * scale
+        off += len(flat)
+        Yo = O.mpk(O.Operator(3, dims[0], dims[1], dims[2], c=C), yw, s, basis,
+                   params=(sg, cc, cd))
+        ref[:, n] = Yo[1:, ctr]
+    for k in range(s):
+        d = np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k])
+        assert d < 1e-13 * (k + 2), k
+    del Y
+    release()
+
+
+# integer-valued periodic columns: x_c[i] = ((i + a_c) mod p_c) - h_c
+XPAT = [(0, 5, 2), (3, 7, 3), (1, 11, 5), (6, 13, 6)]
+ZPAT = [(2, 3, 1), (0, 4, 2), (5, 9, 4), (1, 8, 3)]
+
+
+def fill_pattern(row, pat, chunk=1 << 28):
+    a, p, h = pat
+    for s0 in range(0, N, chunk):
+        s1 = min(N, s0 + chunk)
+        idx = torch.arange(s0, s1, dtype=torch.int64, device=DEV)
+        row[s0:s1] = ((idx + a) % p - h).to(torch.float64)
+        del idx
+
+
+def pattern_at(idx, pat):
+    a, p, h = pat
+    return ((idx + a) % p - h).astype(np.float64)
+
+
+def pattern_dot(px, pz, n):
+    """sum_{i < n} x[i] z[i] for two periodic patterns, in exact integers."""
+    L = math.lcm(px[1], pz[1])
+
+    def part(m):
+        return sum(((i + px[0]) % px[1] - px[2]) * ((i + pz[0]) % pz[1] - pz[2]) for i in range(m))
+
+    return (n // L) * part(L) + part(n % L)
+
+
+def test_block_gram_max_grid_exact():
+    X = torch.zeros((len(XPAT), LD), dtype=torch.float64, device=DEV)
+    Z = torch.zeros((len(ZPAT), LD), dtype=torch.float64, device=DEV)
+    for r, pat in enumerate(XPAT):
+        fill_pattern(X[r], pat)
+    for r, pat in enumerate(ZPAT):
+        fill_pattern(Z[r], pat)
+    G = S.kernel_gram(X[:, :N], Z[:, :N]).cpu().numpy()
+    ref = np.array([[float(pattern_dot(px, pz, N)) for pz in ZPAT] for px in XPAT])
+    assert np.array_equal(G, ref)
+    # the one-pass symmetric kernel on the same columns
+    Gs = S.kernel_gram(X[:, :N], X[:, :N]).cpu().numpy()
+    refs = np.array([[float(pattern_dot(pa, pb, N)) for pb in XPAT] for pa in XPAT])
+    assert np.array_equal(Gs, refs)
+    del X, Z
+    release()
+
+
+def test_block_update_max_grid_exact():
+    X = torch.zeros((len(XPAT), LD), dtype=torch.float64, device=DEV)
+    Y = torch.zeros((len(ZPAT), LD), dtype=torch.float64, device=DEV)
+    for r, pat in enumerate(XPAT):
+        fill_pattern(X[r], pat)
+    for r, pat in enumerate(ZPAT):
+        fill_pattern(Y[r], pat)
+    M = np.array([[1, -2, 3, 0], [2, 1, -1, 4], [-3, 0, 2, 1], [1, 5, -2, -1]], dtype=np.float64)
+    S.kernel_update(X[:, :N], Y[:, :N], torch.from_numpy(M).to(DEV))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(205)
+    rows = np.unique(np.concatenate([np.arange(64), np.arange(N - 64, N),
+                                     rng.integers(0, N, 8192)])).astype(np.int64)
+    ri = torch.from_numpy(rows).to(DEV)
+    got = Y[:, ri].cpu().numpy()
+    xs = np.stack([pattern_at(rows, p) for p in XPAT])
+    ref = np.stack([pattern_at(rows, p) for p in ZPAT]) + M.T @ xs
+    assert np.array_equal(got, ref)
+    del X, Y
+    release()
+
+
+def test_sgmres_cycle_max_grid():
+    A = stencil()
+    g = torch.Generator(device=DEV)
+    g.manual_seed(206)
+    f = torch.empty(N, dtype=torch.float64, device=DEV).uniform_(-1.0, 1.0, generator=g)
+    x = torch.zeros(N, dtype=torch.float64, device=DEV)
+    ws = S.allocate_workspace(A, S.METHOD_GMRES, 2, 2)
+    info = S.gmres_solve(A, f, x, 2, 2, 0.0, max_iters=2, workspace=ws)
+    torch.cuda.synchronize()
+    del ws
+    assert info.status == S.NOT_CONVERGED and info.iters == 2
+    fh = f.cpu().numpy()
+    del f
+    xh = x.cpu().numpy()
+    del x
+    release()
+    r = fh - O.apply(O.Operator(3, NX, NX, NX, c=C), xh)
+    rel = float(np.linalg.norm(r) / np.linalg.norm(fh))
+    assert 0.0 < rel < 1.0
+    assert abs(rel - info.rel_resid) <= 1e-12
