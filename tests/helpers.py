@@ -73,3 +73,20 @@ def stencil_eigpair(prob: PB.Problem, js):
         # x fastest: vec[p] with p = i + nx*(j + ny*l)
         vec = v if vec is None else np.kron(v, vec)
     return lam, vec
+
+
+def window(shape, point, R):
+    """The grid of shape (nx, ny, nz) clipped to the box of radius R around
+    point (i, j, l): its dims, the flat indices of its points (x fastest) and
+    the position of the point inside it.  A stencil value of level <= R at the
+    point depends only on points of this window, and the clipped sides keep
+    the grid's own Dirichlet boundary."""
+    lo = [max(0, v - R) for v in point]
+    hi = [min(n - 1, v + R) for n, v in zip(shape, point)]
+    ax = [np.arange(a, b + 1, dtype=np.int64) for a, b in zip(lo, hi)]
+    nx, ny = shape[0], shape[1]
+    flat = (ax[2][:, None, None] * nx * ny + ax[1][None, :, None] * nx + ax[0][None, None, :]).ravel()
+    dims = [len(a) for a in ax]
+    i, j, l = point
+    ctr = (l - lo[2]) * dims[0] * dims[1] + (j - lo[1]) * dims[0] + (i - lo[0])
+    return dims, flat, ctr

@@ -51,6 +51,31 @@ def test_workspace_sizing_and_argument_checks():
     assert S.workspace_bytes(bad, S.METHOD_GMRES, 4, 4) == 0
 
 
+def test_size_limits_without_launching():
+    # grids up to 2^31 - 1 points are accepted (1290^3), larger ones rejected
+    # (1291^3); empty grids and empty kernel operands are rejected
+    big = S.Stencil(3, 1290, 1290, 1290, (6.0, -1, -1, -1, -1, -1, -1))
+    assert S.workspace_bytes(big, S.METHOD_GMRES, 2, 2) > 5 * 1290 ** 3 * 8
+    over = S.Stencil(3, 1291, 1291, 1291, (6.0, -1, -1, -1, -1, -1, -1))
+    assert S.workspace_bytes(over, S.METHOD_GMRES, 2, 2) == 0
+    assert S.workspace_bytes(S.Stencil(2, 46341, 46341, 1, (4.0, -1, -1, -1, -1, 0, 0)),
+                             S.METHOD_GMRES, 2, 2) == 0
+    lib = S.load()
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    oc = over.c_struct()
+    assert lib.sstep_gmres_solve(C.byref(oc), fake, fake, 2, 2, 1e-8, None, None) == -1
+    assert lib.sstep_omin_solve(C.byref(oc), fake, fake, 2, 2, 1e-8, None, None) == -1
+    assert lib.sstep_stencil_apply(C.byref(oc), fake, C.c_void_p(0x2000), None) == -1
+    for nx, ny, nz in [(0, 5, 5), (5, 0, 5), (5, 5, 0)]:
+        e = S.Stencil(3, nx, ny, nz, (6.0, -1, -1, -1, -1, -1, -1))
+        assert S.workspace_bytes(e, S.METHOD_GMRES, 2, 2) == 0
+    assert lib.sstep_kernel_gram(fake, 0, 3, fake, 0, 3, 0, fake, None) == -1          # N = 0
+    assert lib.sstep_kernel_gram(fake, 64, 0, fake, 64, 3, 64, fake, None) == -1       # no columns
+    assert lib.sstep_kernel_gram(fake, 1 << 31, 3, fake, 1 << 31, 3, 1 << 31, fake, None) == -1
+    assert lib.sstep_kernel_update(fake, 0, 2, fake, 0, 2, fake, 0, None) == -1        # N = 0
+    assert lib.sstep_kernel_update(fake, 64, 2, fake, 64, 0, fake, 64, None) == -1     # no outputs
+
+
 def test_solvers_reject_bad_arguments_without_launching():
     lib = S.load()
     A = S.Stencil(2, 8, 8, 1, (4.0, -1, -1, -1, -1, 0, 0)).c_struct()

@@ -24,6 +24,7 @@ torch = pytest.importorskip("torch")
 import oracle as O
 from paper_2001_04886_amd import problems as PB
 from paper_2001_04886_amd import sstep as S
+from helpers import window as grid_window
 
 pytestmark = pytest.mark.gpu
 
@@ -65,16 +66,7 @@ def sample_points(nrand, seed):
 
 
 def window(i, j, l, R):
-    """Index ranges of the grid clipped to the box of radius R around
-    (i, j, l), the flat indices of its points (x fastest) and the position of
-    (i, j, l) inside it."""
-    lo = [max(0, v - R) for v in (i, j, l)]
-    hi = [min(NX - 1, v + R) for v in (i, j, l)]
-    ax = [np.arange(a, b + 1, dtype=np.int64) for a, b in zip(lo, hi)]
-    flat = (ax[2][:, None, None] * NX * NX + ax[1][None, :, None] * NX + ax[0][None, None, :]).ravel()
-    dims = [len(a) for a in ax]
-    ctr = (l - lo[2]) * dims[0] * dims[1] + (j - lo[1]) * dims[0] + (i - lo[0])
-    return dims, flat, ctr
+    return grid_window((NX, NX, NX), (i, j, l), R)
 
 
 def gather(vec, idx):

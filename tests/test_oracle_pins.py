@@ -6,7 +6,7 @@ import pytest
 
 import oracle as O
 from paper_2001_04886_amd import problems as PB
-from helpers import dense, krylov_min_residual, operator, stencil_eigpair
+from helpers import dense, krylov_min_residual, operator, stencil_eigpair, window
 
 
 def rel(a, b):
@@ -150,6 +150,41 @@ def test_mpk_monomial_and_chebyshev_closed_forms():
     Yc = O.mpk(A, y0, s, O.CHEBYSHEV)
     Qm, _ = np.linalg.qr(Ym.T)
     assert np.linalg.norm(Yc.T - Qm @ (Qm.T @ Yc.T)) < 1e-9 * np.linalg.norm(Yc)
+
+
+@pytest.mark.parametrize("basis", [O.MONOMIAL, O.CHEBYSHEV])
+def test_mpk_is_local_window_reproduces_grid(basis):
+    # level j of the matrix powers at a point depends only on the points
+    # within j grid steps (a (2j+1)-point-wide box, the 7-point stencil
+    # applied j times); the grid clipped to that box, with the full grid's
+    # scaling and interval, gives the same value bit for bit, at the domain
+    # edge as well (clipped sides are the grid's own Dirichlet boundary)
+    nx, ny, nz, s = 14, 11, 9, 4
+    prob = PB.convdiff(3, nx, 50.0, ny=ny, nz=nz)
+    A = operator(prob)
+    y0 = PB.x_true(9, prob.N)
+    sg = O.sigma(A)
+    cc, cd = O.cheb_interval(A)
+    Y = O.mpk(A, y0, s, basis)
+    y1 = O.apply(A, y0)
+    rng = np.random.default_rng(3)
+    pts = [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny // 2, nz - 1), (nx - 2, 1, 4)]
+    pts += [tuple(int(rng.integers(0, n)) for n in (nx, ny, nz)) for _ in range(20)]
+    for pt in pts:
+        p = pt[0] + nx * pt[1] + nx * ny * pt[2]
+        dims, flat, ctr = window((nx, ny, nz), pt, s)
+        W = O.Operator(3, *dims, c=prob.c)
+        Yw = O.mpk(W, y0[flat], s, basis, params=(sg, cc, cd))
+        assert np.array_equal(Yw[:, ctr], Y[:, p]), pt
+        d1, f1, c1 = window((nx, ny, nz), pt, 1)
+        assert O.apply(O.Operator(3, *d1, c=prob.c), y0[f1])[c1] == y1[p], pt
+    # a window one step too narrow does not reproduce the last level (the
+    # check above is not vacuous)
+    pt = (7, 5, 4)
+    dims, flat, ctr = window((nx, ny, nz), pt, s - 1)
+    Yw = O.mpk(O.Operator(3, *dims, c=prob.c), y0[flat], s, basis, params=(sg, cc, cd))
+    p = pt[0] + nx * pt[1] + nx * ny * pt[2]
+    assert Yw[s - 1, ctr] == Y[s - 1, p] and Yw[s, ctr] != Y[s, p]
 
 
 # --------------------------------------------------------------------------
