@@ -276,6 +276,33 @@ def test_nonzero_initial_guess():
     assert rel(xg, xo) <= 1e-8
 
 
+@pytest.mark.parametrize("method,kw", [
+    ("gmres", {}), ("gmres", {"precision": S.MIXED}), ("gmres", {"basis": S.NEWTON}),
+    ("gmres", {"graph": True}), ("gmres", {"precond": S.PRECOND_ILU0}),
+    ("omin", {}), ("omin", {"orth": S.ORTH_MGS}), ("omin", {"precond": S.PRECOND_ILU0})])
+def test_initial_guess_already_converged(method, kw):
+    # x0 = x_true with f = A x_true (built by the oracle): the initial true
+    # residual is at rounding level, so every form stops before its first
+    # block / iteration and returns x0 (up to the round trip through the
+    # preconditioned unknown u = LU x)
+    if "precond" in kw:
+        prob = PB.convdiff(2, 37, 30.0, ny=23, seed=12)
+    else:
+        prob = PB.convdiff(3, 13, 30.0, ny=11, nz=9, seed=12)
+    Ao, Ag = problem_pair(prob)
+    xt = prob.x_true()
+    f = O.apply(Ao, xt)
+    x = dev(xt.copy())
+    if method == "gmres":
+        info = S.gmres_solve(Ag, dev(f), x, 4, 5, 1e-8, **kw)
+    else:
+        info = S.omin_solve(Ag, dev(f), x, 4, 3, 1e-8, **kw)
+    assert info.status == S.OK
+    assert info.iters == 0
+    assert info.rel_resid <= 1e-12
+    assert rel(host(x), xt) <= 1e-12
+
+
 def test_error_paths():
     prob = PB.convdiff(2, 16, 10.0)
     Ao, Ag = problem_pair(prob)
