@@ -12,9 +12,10 @@ Solvers at full size: the oracle cannot run these solves in seconds, so each
 is checked by a property that holds at any size: the true residual
 ||f - A x|| / ||f||, recomputed on the CPU by the oracle's FP64 operator from
 the returned x, is within the requested tolerance (eq. (1) stopping test) and
-agrees with the residual the library reports.  Right-hand sides are built by
-the oracle operator as well (f = A x_true), so no input comes from the HIP
-path."""
+agrees with the residual the library reports; the FP64 s-GMRES and s-Omin
+solves are repeated and must return the same bits (fixed-order reductions).
+Right-hand sides are built by the oracle operator as well (f = A x_true), so
+no input comes from the HIP path."""
 import numpy as np
 import pytest
 
@@ -174,9 +175,15 @@ def test_headline_sgmres_true_residual(cube):
     info = S.gmres_solve(Ag, dev(f), x, 8, 40, 1e-8, workspace=ws, profile=True)
     assert info.status == S.OK
     assert info.rel_resid <= 1e-8
-    r = true_residual(Ao, f, host(x))
+    xh = host(x)
+    r = true_residual(Ao, f, xh)
     assert r <= 1e-8 * (1 + 1e-6)
     assert abs(r - info.rel_resid) <= 1e-13
+    # deterministic reductions: a second solve returns the same bits
+    x.zero_()
+    info2 = S.gmres_solve(Ag, dev(f), x, 8, 40, 1e-8, workspace=ws, profile=True)
+    assert (info2.iters, info2.cycles, info2.rel_resid) == (info.iters, info.cycles, info.rel_resid)
+    assert np.array_equal(host(x), xh)
     del ws, x
     release()
 
@@ -208,9 +215,15 @@ def test_omin_4096sq_true_residual():
     x = torch.zeros(prob.N, dtype=torch.float64, device=DEV)
     info = S.omin_solve(Ag, dev(f), x, 8, 8, 1e-8, max_iters=600, workspace=ws, profile=True)
     assert info.status == S.OK
-    r = true_residual(Ao, f, host(x))
+    xh = host(x)
+    r = true_residual(Ao, f, xh)
     assert r <= 1e-8 * (1 + 1e-6)
     assert abs(r - info.rel_resid) <= 1e-13
+    # deterministic reductions: a second solve returns the same bits
+    x.zero_()
+    info2 = S.omin_solve(Ag, dev(f), x, 8, 8, 1e-8, max_iters=600, workspace=ws, profile=True)
+    assert (info2.iters, info2.rel_resid) == (info.iters, info.rel_resid)
+    assert np.array_equal(host(x), xh)
     del ws, x
     release()
 
