@@ -88,3 +88,28 @@ def test_dependent_column_is_dropped():
     x, r = O.somin(A, g, np.zeros(20), 4, 1, 1e-12, max_iters=5, mgs=True)
     assert r.status == O.OK and r.iters == 1
     np.testing.assert_allclose(x, g, rtol=1e-13)
+
+
+@pytest.mark.parametrize("delta,kept", [(1e-9, [True, False, False, False]),
+                                        (1e-3, [True, True, True, False])])
+def test_nearly_dependent_columns_are_dropped(delta, kept):
+    # A = diag(1 + delta d): consecutive Krylov columns differ by O(delta), so
+    # after A^T A-orthogonalisation column q keeps about delta^(2q) of its
+    # squared A-norm.  Columns below the drop threshold (1e-14 of the value
+    # before orthogonalisation) must be exactly zero in both P and AP, the
+    # others kept: delta = 1e-9 leaves only column 0; delta = 1e-3 keeps
+    # columns 1 (~1e-6) and 2 (~1e-12) and drops column 3 (~1e-18).
+    nx, ny, s = 6, 5, 4
+    N = nx * ny
+    coef = np.zeros((7, N))
+    coef[0] = 1.0 + delta * np.linspace(-1.0, 1.0, N)
+    A = O.Operator(2, nx, ny, coef=coef)
+    g = np.cos(np.arange(N))
+    x, r, P, AP, _ = O.somin(A, g, np.zeros(N), s, 1, 0.0, max_iters=1, dump=True, mgs=True)
+    for q in range(s):
+        if kept[q]:
+            assert np.linalg.norm(AP[q]) > 0.0 and np.linalg.norm(P[q]) > 0.0, q
+        else:
+            assert not AP[q].any() and not P[q].any(), q
+    # the kept directions still satisfy A P = AP
+    np.testing.assert_allclose(O.apply(A, P[0]), AP[0], rtol=1e-13)
