@@ -83,6 +83,26 @@ def test_dependent_block():
     np.testing.assert_allclose(x.cpu().numpy(), g.cpu().numpy(), rtol=1e-13)
 
 
+@pytest.mark.parametrize("delta", [1e-9, 1e-3])
+def test_nearly_dependent_columns(delta):
+    # A = diag(1 + delta d): column q of a block keeps about delta^(2q) of its
+    # squared A-norm after orthogonalisation, so delta = 1e-9 drops columns
+    # 1..3 of every block and delta = 1e-3 drops column 3 (two decades from
+    # the 1e-14 threshold either way); fixed work against the oracle
+    print(f"omin mgs nearly dependent delta={delta}", flush=True)
+    nx, ny, s = 6, 5, 4
+    N = nx * ny
+    coef = np.zeros((7, N))
+    coef[0] = 1.0 + delta * np.linspace(-1.0, 1.0, N)
+    Ao = O.Operator(2, nx, ny, coef=coef)
+    cd = torch.from_numpy(coef).cuda()
+    Ag = S.Stencil(2, nx, ny, 1, (0.0,) * 7, cd)
+    g = np.cos(np.arange(N))
+    xg, info, xo, res = run(Ag, Ao, g, np.zeros(N), s, 1, 0.0, 3)
+    assert info.iters == res.iters == 3
+    assert rel(xg, xo) <= 1e-12
+
+
 def test_argument_errors():
     print("omin mgs argument errors", flush=True)
     pr, Ao, Ag, keep = paper_pair(16)
