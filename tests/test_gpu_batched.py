@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 import oracle as O
 from paper_2001_04886_amd import problems as PB
 from paper_2001_04886_amd import sstep as S
-from helpers import operator
+from helpers import operator, stencil_eigpair
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -123,6 +123,39 @@ def test_batched_mixed_dimensions_and_isolation_of_failures():
             assert info.status == S.ERR_NONFINITE
         else:
             assert info.status == S.OK and info.rel_resid <= 1e-10
+
+
+def test_batched_degenerate_members():
+    # one batch holding a zero right-hand side (x = 0 is exact: no block), an
+    # eigenvector right-hand side (lucky breakdown after one block, x = v /
+    # lambda), an initial guess that is already exact (no block, x kept) and
+    # an ordinary system (against the oracle); each member ends on its own
+    pz = PB.convdiff(2, 12, 10.0, seed=1)
+    pe = PB.convdiff(2, 16, 20.0, ny=12, seed=2)
+    px = PB.convdiff(2, 20, 30.0, seed=3)
+    pn = PB.convdiff(2, 24, 40.0, seed=4)
+    lam, v = stencil_eigpair(pe, [2, 3])
+    probs = [pz, pe, px, pn]
+    fs = [np.zeros(pz.N), v, O.apply(operator(px), px.x_true()), O.apply(operator(pn), pn.x_true())]
+    x0s = [np.zeros(pz.N), np.zeros(pe.N), px.x_true(), np.zeros(pn.N)]
+    st = [S.Stencil.from_problem(p) for p in probs]
+    fd = [torch.from_numpy(f).to(DEV) for f in fs]
+    xd = [torch.from_numpy(x.copy()).to(DEV) for x in x0s]
+    plan = S.BatchPlan(st, fd, xd, 4, 10, 1e-10, graph=True)
+    try:
+        status, infos = plan.execute()
+    finally:
+        plan.close()
+    torch.cuda.synchronize()
+    xs = [x.cpu().numpy() for x in xd]
+    assert status == S.OK
+    assert all(i.status == S.OK for i in infos)
+    assert infos[0].iters == 0 and not xs[0].any()
+    assert infos[1].iters == 1 and rel(xs[1], v / lam) <= 1e-12
+    assert infos[2].iters == 0 and rel(xs[2], px.x_true()) <= 1e-12
+    xo, res = O.sgmres(operator(pn), fs[3], np.zeros(pn.N), 4, 10, 1e-10)
+    assert infos[3].rel_resid <= 1e-10 and abs(infos[3].iters - res.iters) <= 1
+    assert rel(xs[3], xo) <= 1e-8
 
 
 def test_batched_argument_checks():
