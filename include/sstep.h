@@ -54,7 +54,11 @@ typedef enum {
  * (neighbours outside are dropped: homogeneous Dirichlet) plus c[0] * x[p].
  * Coefficient order: 0 centre, 1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z.
  * If coef != NULL it is a DEVICE array [7][N] of per-point coefficients in
- * the same order (variable coefficients) and c[] is ignored. */
+ * the same order (variable coefficients) and c[] is ignored.
+ * Sizes: nx, ny (and nz) >= 1 and N = nx * ny * nz <= 2^31 - 1 grid points
+ * (16 GiB per FP64 vector; 1290^3 is the largest cube); a larger or empty
+ * grid is SSTEP_ERR_ARG before anything is launched. Unknowns are numbered
+ * x fastest: p = i + nx * (j + ny * l). */
 typedef struct {
     int32_t ndim;               /* 2 or 3                                         */
     int32_t nx, ny, nz;         /* interior points per axis; nz ignored for ndim 2 */
