@@ -48,6 +48,7 @@ struct GmState {
     // cycle state
     double beta, est, stop_abs, yhat2, nu_cur;
     int kb, ncols, done, skip_n4b, skip_asm, active, conv, err, blocks_total, cycles, lucky;
+    int asm_cols;  // columns combined by the last solution assembly
     double g[kMaxS], coefN4b[kMaxS];
     double nu[kMaxBlocks + 1], inv_nu[kMaxBlocks + 1];
 };
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_cycle_start(GmArrays a,
         const double beta = sqrt(o[0]);
         st->beta = beta;
         st->kb = 0;
+        st->asm_cols = st->ncols;
         st->ncols = 0;
         st->lucky = 0;
         st->skip_n4b = 1;
@@ -583,7 +585,7 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
         c.end();
     };
     struct Ret {
-        int conv, err, blocks_total, cycles, ncols, kb;
+        int conv, err, blocks_total, cycles, ncols, kb, asm_cols;
         double est, beta, fnorm, tol_abs;
     } ret{};
     auto read_state = [&]() {
@@ -596,6 +598,7 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
         ret.cycles = hs.cycles;
         ret.ncols = hs.ncols;
         ret.kb = hs.kb;
+        ret.asm_cols = hs.asm_cols;
         ret.est = hs.est;
         ret.beta = hs.beta;
         ret.fnorm = hs.fnorm;
@@ -654,6 +657,9 @@ static int gmres_run(Ctx& c, const sstep_stencil& Ast, const double* f, double* 
         const int ran = ret.blocks_total - before;
         matvecs += ran * s + 1;
         c.harvest(ran);
+        // the assembly's column count was known only on the device: x (FP64)
+        // and asm_cols basis columns read, x written
+        c.add_bytes(SSTEP_K_VEC, ((double)ret.asm_cols * sizeof(T) + 16.0) * (double)N);
         last_est = ret.est;
     }
     if (info) {

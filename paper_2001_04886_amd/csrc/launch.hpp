@@ -128,6 +128,10 @@ struct Ctx {
         if (!profile) return;
         SSTEP_HIP(hipEventRecord(next_event(), st));
     }
+    // algorithmic bytes of a launch whose size was only known after it ran
+    void add_bytes(int cls, double b) {
+        if (profile) bytes[cls] += b;
+    }
     // after a stream synchronize: fold records of executed blocks into totals
     // (blocks_done: blocks of the cycle that ran; launches of later blocks
     // exited at their first instruction and are not counted).

@@ -364,7 +364,14 @@ def test_somin_small_workload_converges(basis):
 
 @pytest.mark.parametrize("basis,s,m,tolx", [(O.MONOMIAL, 1, 8, 1e-10), (O.MONOMIAL, 2, 5, 1e-10),
                                             (O.MONOMIAL, 4, 3, 1e-10), (O.CHEBYSHEV, 4, 3, 1e-10),
-                                            (O.CHEBYSHEV, 6, 2, 1e-10)])
+                                            (O.CHEBYSHEV, 6, 2, 1e-10),
+                                            # the configured block sizes: monomial s = 8 (a
+                                            # 9-column power basis, conditioning ~1e8: measured
+                                            # 4e-8 here), Chebyshev and Newton s = 8 and 12
+                                            # (measured <= 3e-14)
+                                            (O.MONOMIAL, 8, 3, 1e-6), (O.MONOMIAL, 8, 2, 1e-6),
+                                            (O.CHEBYSHEV, 8, 3, 1e-10), (O.CHEBYSHEV, 12, 2, 1e-10),
+                                            (O.NEWTON, 8, 3, 1e-10), (O.NEWTON, 12, 2, 1e-10)])
 def test_sgmres_cycle_is_gmres_ms_minimiser(basis, s, m, tolx):
     # Remark 4.1: one cycle of s-GMRES(m) gives the GMRES(ms) iterate
     prob, A, M, f = _tiny(gamma=10.0, nx=9, ny=8)
