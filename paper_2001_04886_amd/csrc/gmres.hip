@@ -107,7 +107,9 @@ __global__ __launch_bounds__(kThreads) void k_gm_cycle_start(GmArrays a,
         const double beta = sqrt(o[0]);
         st->beta = beta;
         st->kb = 0;
-        st->asm_cols = st->ncols;
+        // a vector load: a scalar load of ncols is not ordered before the
+        // vector store that clears it below
+        st->asm_cols = __atomic_load_n(&st->ncols, __ATOMIC_RELAXED);
         st->ncols = 0;
         st->lucky = 0;
         st->skip_n4b = 1;

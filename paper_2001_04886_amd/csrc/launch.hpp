@@ -18,6 +18,7 @@
 #include "gram_self.hpp"
 #include "kernels.hpp"
 #include "mpk.hpp"
+#include "mpk3d.hpp"
 
 namespace sstep {
 
@@ -400,6 +401,71 @@ inline void mpk_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T
                            in_scale, prev, prev_scale, lv, g.ntx, g.nty, g.zchunk, skip);
 }
 
+// 3-D constant-coefficient matrix powers (mpk3d.hpp): up to kMpk3L levels per
+// pass on tiles of 64 x 64 points (56 x 56 exact).  Tile shape per variant:
+// 4 rows x 16 waves, or 4 rows x 8 waves when the first level also reads
+// y_{-1} (more registers per row).
+constexpr int kMpk3L = 4;
+using Mpk3Geom = Mpk3Tile<kMpk3L, 4, 16>;
+static_assert(Mpk3Tile<kMpk3L, 4, 8>::IX == Mpk3Geom::IX, "same x interior");
+
+inline bool mpk3_applies(const StencilView& v) { return v.ndim == 3 && !v.coef && mpk_fused_fits(v); }
+
+// Grids too small for the register-tile kernel: fewer than 128 workgroups even
+// with the shortest chunks.
+inline bool mpk3_small_grid(const StencilView& v) {
+    const long long tiles = (long long)((v.nx + Mpk3Geom::IX - 1) / Mpk3Geom::IX) *
+                            ((v.ny + Mpk3Geom::IY - 1) / Mpk3Geom::IY);
+    return tiles * ((v.nz + 2 * kMpk3L - 1) / (2 * kMpk3L)) < 128;
+}
+
+template <typename T, int L, int POS, int W, bool PREV, bool UNI>
+inline void mpk3_launch(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
+                        const double* in_scale, const T* prev, const double* prev_scale,
+                        const MpkLevels& lv, const int* skip) {
+    using G = Mpk3Tile<L, POS, W>;
+    const auto kern = k_mpk3d<T, L, POS, W, PREV, UNI>;
+    const int ntx = (v.nx + G::IX - 1) / G::IX, nty = (v.ny + G::IY - 1) / G::IY;
+    const long long tiles = (long long)ntx * nty;
+    // chunks along z: minimise (rounds of resident workgroups) x (steps per
+    // workgroup), the time of the most loaded compute unit
+    static const int occ = [&] {  // resident workgroups per compute unit, queried once
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, G::THREADS, 0) != hipSuccess)
+            n = 1;
+        return std::max(1, n);
+    }();
+    const long long slots = (long long)device_cus() * occ;
+    int zchunk = v.nz;
+    long long best = -1;
+    for (int n = 1; n <= std::max(1, v.nz / (2 * L)); ++n) {
+        const int zc = (v.nz + n - 1) / n;
+        const long long nzc = (v.nz + zc - 1) / zc;
+        const long long cost = ((tiles * nzc + slots - 1) / slots) * (zc + 2 * L);
+        if (best < 0 || cost < best) {
+            best = cost;
+            zchunk = zc;
+        }
+    }
+    const int nzc = (v.nz + zchunk - 1) / zchunk;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nzc)), dim3(G::THREADS), 0, c.st, v, out0,
+                       ldo, in, in_scale, prev, prev_scale, lv, ntx, nty, zchunk, skip);
+}
+
+template <typename T, int L>
+inline void mpk3_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
+                    const double* in_scale, const T* prev, const double* prev_scale,
+                    const MpkLevels& lv, const int* skip) {
+    bool uni = true;
+    for (int j = 1; j < L; ++j) uni = uni && lv.alpha[j] == lv.alpha[0];
+    const bool pv = prev != nullptr && lv.gam[0] != 0.0;
+    if (pv && !uni) throw HipFailure{hipErrorInvalidValue, "mpk3 level scales"};
+    constexpr int WP = sizeof(T) == 8 ? 8 : 16;  // waves with y_{-1}
+    if (pv) mpk3_launch<T, L, 4, WP, true, true>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
+    else if (uni) mpk3_launch<T, L, 4, 16, false, true>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
+    else mpk3_launch<T, L, 4, 16, false, false>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
+}
+
 // Level coefficients of the monomial / Chebyshev recurrence at global level
 // lev = 1..s: y_lev = alpha A y_{lev-1} + beta y_{lev-1} + gam y_{lev-2}.
 inline void mpk_level_coefs(int lev, int basis, const OpParams& P, double* a, double* b,
@@ -460,8 +526,10 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
             return;
         }
     }
+    const bool r3 = mpk3_applies(v);
     const int L0 = v.ndim == 3 ? std::min(s, 2) : (s >= 8 ? 8 : (s >= 6 ? 6 : (s >= 4 ? 4 : s)));
-    if ((!fused_only && mpk_small_grid(v, L0)) || !mpk_fused_fits(v)) {
+    const bool small = r3 ? mpk3_small_grid(v) : mpk_small_grid(v, L0);
+    if ((!fused_only && small) || !mpk_fused_fits(v)) {
         for (int lev = 1; lev <= s; ++lev) {
             double a, b, g;
             mpk_level_coefs(lev, basis, P, &a, &b, &g);
@@ -477,10 +545,12 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
     int j0 = 0;
     while (j0 < s) {
         const int left = s - j0;
-        // 2-D: up to 8 levels per pass; 3-D: 2 levels per pass (deeper fusion
-        // of the 7-point stencil loses more to halo recomputation than it saves)
-        const int L = v.ndim == 3 ? std::min(left, 2)
-                                  : (left >= 8 ? 8 : (left >= 6 ? 6 : (left >= 4 ? 4 : left)));
+        // 2-D: up to 8 levels per pass; 3-D constant coefficients: up to 4
+        // (mpk3d.hpp); 3-D variable coefficients: 2 (seven coefficient planes
+        // per level are loaded too)
+        const int L = r3 ? std::min(left, kMpk3L)
+                         : v.ndim == 3 ? std::min(left, 2)
+                                       : (left >= 8 ? 8 : (left >= 6 ? 6 : (left >= 4 ? 4 : left)));
         MpkLevels lv;
         for (int j = 0; j < L; ++j)  // global level index j0 + j + 1
             mpk_level_coefs(j0 + j + 1, basis, P, &lv.alpha[j], &lv.beta[j], &lv.gam[j]);
@@ -492,7 +562,14 @@ inline void launch_mpk(Ctx& c, const StencilView& v, T* Y, long long ldy, int s,
         // algorithmic bytes of the whole MPK call: read 1, write s
         c.begin(SSTEP_K_MPK, vb * (L + (j0 == 0 ? 1.0 : 0.0)));
 #define SSTEP_MPK(D, LL) mpk_go<T, D, LL>(c, v, out0, ldy, in, isc, prev, psc, lv, skip)
-        if (v.ndim == 3) {
+        if (r3) {
+            switch (L) {
+                case 4: mpk3_go<T, 4>(c, v, out0, ldy, in, isc, prev, psc, lv, skip); break;
+                case 3: mpk3_go<T, 3>(c, v, out0, ldy, in, isc, prev, psc, lv, skip); break;
+                case 2: mpk3_go<T, 2>(c, v, out0, ldy, in, isc, prev, psc, lv, skip); break;
+                default: mpk3_go<T, 1>(c, v, out0, ldy, in, isc, prev, psc, lv, skip); break;
+            }
+        } else if (v.ndim == 3) {
             if (L == 2) SSTEP_MPK(3, 2);
             else SSTEP_MPK(3, 1);
         } else {
