@@ -26,7 +26,8 @@
  *     launch.  No exception crosses the boundary.
  *   - Calls on different streams are independent; the library holds no
  *     mutable global state besides a lazily created per-device stream-less
- *     kernel configuration.
+ *     kernel configuration and the per-GPU scratch array of
+ *     sstep_gmres_solve_noalloc (shared by that entry point's calls only).
  */
 #ifndef SSTEP_H
 #define SSTEP_H
@@ -178,6 +179,31 @@ size_t sstep_workspace_bytes(const sstep_stencil *A, int method, int s, int k_or
  * (max_iters blocks built) or an error. */
 int sstep_gmres_solve(const sstep_stencil *A, const double *f, double *x, int s, int m,
                       double tol, const sstep_options *opt, sstep_info *info);
+
+/* Largest workspace sstep_gmres_solve_noalloc serves (bytes): 128 MiB, the
+ * size of the library's static per-GPU scratch array.  For example s-GMRES
+ * (m = 30, s = 8) on a 256 x 256 grid needs about 127 MB. */
+#define SSTEP_NOALLOC_MAX_WORKSPACE ((size_t)134217728)
+
+/* sstep_gmres_solve for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation): the same method, kernels
+ * and results, with the workspace taken from a static device array of
+ * SSTEP_NOALLOC_MAX_WORKSPACE bytes that the library holds on every GPU it
+ * runs on until the process ends.  No hipMalloc / hipFree, no event or
+ * stream creation.  Arguments as sstep_gmres_solve, plus:
+ *   - opt->workspace must be NULL, opt->profile and opt->graph 0
+ *     (SSTEP_ERR_ARG otherwise); info->ms_total is not measured (0);
+ *   - a solve whose workspace (sstep_workspace_bytes, plus
+ *     sstep_precond_workspace_bytes with ILU(0)) exceeds
+ *     SSTEP_NOALLOC_MAX_WORKSPACE returns SSTEP_ERR_NOMEM before anything is
+ *     launched; x is then untouched.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (other host threads, other streams) race and must be serialised by the
+ * caller.  The solve never reads workspace it has not written in the same
+ * call, so nothing has to be cleared between calls.  The call synchronises
+ * opt->stream once per restart cycle, like sstep_gmres_solve. */
+int sstep_gmres_solve_noalloc(const sstep_stencil *A, const double *f, double *x, int s, int m,
+                              double tol, const sstep_options *opt, sstep_info *info);
 
 /* s-step Orthomin(k) (Sec. 3, Alg. 3.1).  Solves A x = f.
  *   s : block size 1..16 (s = 1 is Omin(k));  k : window of previous

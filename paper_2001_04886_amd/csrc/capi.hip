@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/sstep.h"
 #include "dense.hpp"
@@ -155,6 +156,39 @@ int precond_solve(Ctx& c, const sstep_stencil& A, double* x, const sstep_options
 }
 }  // namespace
 
+// Workspace of sstep_gmres_solve_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name
+// as an address (on the host it is a stand-in, not a device pointer): the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is what the kernels receive.
+static __device__ __align__(256) unsigned char scratch[SSTEP_NOALLOC_MAX_WORKSPACE];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device, null until set up
+
+// Device address of the current device's scratch array (set up on first use).
+int scratch_ptr(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return SSTEP_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SSTEP_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SSTEP_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void sstep_default_options(sstep_options* opt) {
@@ -189,32 +223,73 @@ size_t sstep_workspace_bytes(const sstep_stencil* A, int method, int s, int k_or
     return 0;
 }
 
-int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s, int m,
-                      double tol, const sstep_options* opt, sstep_info* info) {
+static bool gmres_args_ok(const sstep_stencil* A, const double* f, const double* x, int s, int m,
+                          double tol, const sstep_options* opt) {
     const int prec = opt ? opt->precision : SSTEP_FP64;
     const int basis = opt ? opt->basis : SSTEP_BASIS_MONOMIAL;
-    if (!stencil_ok(A) || !f || !x || ((uintptr_t)f & 15u) || ((uintptr_t)x & 15u) || s < 1 ||
-        s > kMaxS || m < 1 || (long long)m * s > 2048 ||
-        !(tol >= 0.0) || (prec != SSTEP_FP64 && prec != SSTEP_MIXED) ||
-        (basis != SSTEP_BASIS_MONOMIAL && basis != SSTEP_BASIS_CHEBYSHEV &&
-         basis != SSTEP_BASIS_NEWTON) ||
-        (opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0) ||
-                 opt->orth != SSTEP_ORTH_CHOL)) ||
-        !precond_ok(A, opt, prec, basis)) {
+    return stencil_ok(A) && f && x && !((uintptr_t)f & 15u) && !((uintptr_t)x & 15u) && s >= 1 &&
+           s <= kMaxS && m >= 1 && (long long)m * s <= 2048 && tol >= 0.0 &&
+           (prec == SSTEP_FP64 || prec == SSTEP_MIXED) &&
+           (basis == SSTEP_BASIS_MONOMIAL || basis == SSTEP_BASIS_CHEBYSHEV ||
+            basis == SSTEP_BASIS_NEWTON) &&
+           !(opt && (opt->max_iters < 0 || !(opt->sigma >= 0.0) || !(opt->inner_tol >= 0.0) ||
+                     opt->orth != SSTEP_ORTH_CHOL)) &&
+           precond_ok(A, opt, prec, basis);
+}
+
+// Workspace of an s-GMRES solve: the method's part, then the preconditioner's.
+static size_t gmres_need(const sstep_stencil& A, int s, int m, const sstep_options* opt,
+                         size_t* base) {
+    *base = gmres_workspace_bytes(A, s, m, opt ? opt->precision : SSTEP_FP64);
+    const bool pc = opt && opt->precond == SSTEP_PRECOND_ILU0;
+    return *base + (pc ? ilu0_workspace(A) : 0);
+}
+
+static int gmres_dispatch(Ctx& c, const sstep_stencil& A, const double* f, double* x, int s, int m,
+                          double tol, const sstep_options& o, sstep_info* info, void* ws,
+                          size_t wsb, size_t base) {
+    if (o.precond != SSTEP_PRECOND_ILU0) return gmres_solve_impl(c, A, f, x, s, m, tol, o, info, ws, wsb);
+    return precond_solve(c, A, x, o, (char*)ws + base, [&](double* u, const sstep_options& o2) {
+        return gmres_solve_impl(c, A, f, u, s, m, tol, o2, info, ws, base);
+    });
+}
+
+int sstep_gmres_solve(const sstep_stencil* A, const double* f, double* x, int s, int m,
+                      double tol, const sstep_options* opt, sstep_info* info) {
+    if (!gmres_args_ok(A, f, x, s, m, tol, opt)) {
         if (info) std::memset(info, 0, sizeof(*info));
         return set_status(info, SSTEP_ERR_ARG);
     }
-    const size_t base = gmres_workspace_bytes(*A, s, m, prec);
-    const bool pc = opt && opt->precond == SSTEP_PRECOND_ILU0;
-    const size_t need = base + (pc ? ilu0_workspace(*A) : 0);
+    size_t base = 0;
+    const size_t need = gmres_need(*A, s, m, opt, &base);
     const sstep_stencil Acopy = *A;
     return run_solver(opt, need, info, [&](Ctx& c, const sstep_options& o, void* ws, size_t wsb) {
-        if (!pc) return gmres_solve_impl(c, Acopy, f, x, s, m, tol, o, info, ws, wsb);
-        return precond_solve(c, Acopy, x, o, (char*)ws + base,
-                             [&](double* u, const sstep_options& o2) {
-                                 return gmres_solve_impl(c, Acopy, f, u, s, m, tol, o2, info, ws,
-                                                         base);
-                             });
+        return gmres_dispatch(c, Acopy, f, x, s, m, tol, o, info, ws, wsb, base);
+    });
+}
+
+int sstep_gmres_solve_noalloc(const sstep_stencil* A, const double* f, double* x, int s, int m,
+                              double tol, const sstep_options* opt, sstep_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (!gmres_args_ok(A, f, x, s, m, tol, opt) ||
+        (opt && (opt->workspace || opt->profile || opt->graph)))
+        return set_status(info, SSTEP_ERR_ARG);
+    size_t base = 0;
+    const size_t need = gmres_need(*A, s, m, opt, &base);
+    if (need > SSTEP_NOALLOC_MAX_WORKSPACE) return set_status(info, SSTEP_ERR_NOMEM);
+    sstep_options o;
+    if (opt) o = *opt;
+    else sstep_default_options(&o);
+    const sstep_stencil Acopy = *A;
+    return guarded(info, [&]() -> int {
+        void* ws = nullptr;
+        const int st = scratch_ptr(&ws);
+        if (st != SSTEP_OK) return st;
+        Ctx c;
+        c.st = (hipStream_t)o.stream;
+        c.profile = false;  // no timing events
+        return gmres_dispatch(c, Acopy, f, x, s, m, tol, o, info, ws, SSTEP_NOALLOC_MAX_WORKSPACE,
+                              base);
     });
 }
 

@@ -28,7 +28,7 @@ KERNEL_CLASSES = ("mpk", "gram", "update", "resid", "scalar", "vec")
 # every symbol declared in include/sstep.h
 EXPORTS = (
     "sstep_default_options", "sstep_status_string", "sstep_workspace_bytes",
-    "sstep_gmres_solve", "sstep_omin_solve", "sstep_stencil_apply",
+    "sstep_gmres_solve", "sstep_gmres_solve_noalloc", "sstep_omin_solve", "sstep_stencil_apply",
     "sstep_kernel_mpk", "sstep_kernel_gram", "sstep_kernel_update",
     "sstep_batch_workspace_bytes", "sstep_batch_plan_create", "sstep_batch_plan_execute",
     "sstep_batch_plan_destroy", "sstep_gmres_solve_batched",
@@ -85,6 +85,8 @@ def load(path: str | None = None):
     lib.sstep_workspace_bytes.restype = C.c_size_t
     lib.sstep_gmres_solve.argtypes = [sp, vp, vp, i32, i32, dp, op_, ip]
     lib.sstep_gmres_solve.restype = i32
+    lib.sstep_gmres_solve_noalloc.argtypes = [sp, vp, vp, i32, i32, dp, op_, ip]
+    lib.sstep_gmres_solve_noalloc.restype = i32
     lib.sstep_omin_solve.argtypes = [sp, vp, vp, i32, i32, dp, op_, ip]
     lib.sstep_omin_solve.restype = i32
     lib.sstep_stencil_apply.argtypes = [sp, vp, vp, vp]
@@ -288,6 +290,20 @@ def gmres_solve(A: Stencil, f, x, s: int, m: int, tol: float, **kw) -> Info:
     o = options(**kw)
     load().sstep_gmres_solve(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, m, tol,
                              C.byref(o), C.byref(info))
+    return Info.from_c(info)
+
+
+NOALLOC_MAX_WORKSPACE = 134217728  # bytes, SSTEP_NOALLOC_MAX_WORKSPACE
+
+
+def gmres_solve_noalloc(A: Stencil, f, x, s: int, m: int, tol: float, **kw) -> Info:
+    """sstep_gmres_solve on the library's static per-GPU workspace (no
+    allocation); x updated in place."""
+    sc = A.c_struct()
+    info = InfoC()
+    o = options(**kw)
+    load().sstep_gmres_solve_noalloc(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, m, tol,
+                                     C.byref(o), C.byref(info))
     return Info.from_c(info)
 
 
