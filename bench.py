@@ -39,6 +39,27 @@ def vec_passes_gmres(blocks_per_cycle, s):
     return tot
 
 
+def flops_gmres(blocks_per_cycle, s, N, ndim):
+    """Algorithmic floating-point operations per kernel class of s-step GMRES
+    cycles (FP64 or FP32 alike): a (2q-1)-flop stencil row of q points, 2 per
+    multiply-add of the Gram and update contractions."""
+    st = 2 * (2 * ndim + 1) - 1                  # 13 (7-point) or 9 (5-point)
+    fl = dict(mpk=0.0, gram=0.0, update=0.0, resid=0.0, scalar=0.0, vec=0.0)
+    fl["vec"] += 2.0 * N                         # ||f||
+    fl["resid"] += (st + 3.0) * N                # r = f - A x and ||r||^2, initial
+    for nb in blocks_per_cycle:
+        for k in range(1, nb + 1):
+            fl["mpk"] += st * s * N
+            if k > 1:
+                fl["gram"] += 2.0 * (k - 1) * s * s * N
+                fl["update"] += 2.0 * (k - 1) * s * s * N
+            fl["vec"] += (s + 1) * (s + 2) * N   # distinct entries of the block's own Gram
+            fl["vec"] += 2.0 * s * N + 2.0 * N   # next start vector and its norm
+        fl["vec"] += 2.0 * nb * s * N            # x = x0 + V y
+        fl["resid"] += (st + 3.0) * N            # true residual of the cycle
+    return fl
+
+
 def kernel_source_hash():
     import glob
     import hashlib
@@ -99,6 +120,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the GMRES(ms) comparator")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle sample")
     ap.add_argument("--cpu-blocks", type=int, default=2)
+    ap.add_argument("--oracle-n", type=int, default=64,
+                    help="grid side on which mixed3d compares every result with the oracle")
+    ap.add_argument("--cpu-n", type=int, default=96,
+                    help="grid side of the all-core oracle timing (one full restart cycle)")
     ap.add_argument("--workload", choices=["gmres3d", "mixed3d", "omin2d", "small2d", "batched",
                                            "learned", "paper2d"],
                     default="gmres3d")
@@ -169,6 +194,10 @@ def main():
         classes[k] = {"ms": ms / args.steps, "launches": nl // args.steps,
                       "GBs": (by / (ms * 1e-3) / 1e9) if ms > 0 and by > 0 else None,
                       "bytes": by / args.steps}
+    fl = flops_gmres(blocks_per_cycle(last.iters, last.cycles, args.m), args.s, N, 3)
+    for k in classes:
+        classes[k]["GFLOPs"] = (fl[k] / (classes[k]["ms"] * 1e-3) / 1e9
+                                if classes[k]["ms"] > 0 and fl[k] > 0 else None)
     dom = max(("gram", "update", "mpk"), key=lambda k: classes[k]["ms"])
     dom_gbs = classes[dom]["GBs"] or 0.0
     traffic = measured_traffic(dom)
@@ -196,6 +225,9 @@ def main():
         "rel_resid": last.rel_resid,
         "x_err_vs_true": xerr,
         "algorithmic_GBs_solve": total_bytes / (ms_per_step * 1e-3) / 1e9,
+        "GFLOPs_solve": sum(fl.values()) / (ms_per_step * 1e-3) / 1e9,
+        "flop_per_solve": sum(fl.values()),
+        "fp64_vector_peak_TFLOPs": 78.6,
         "kernels": classes,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": dom_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_gbs / HBM_PEAK_GBS, "traffic": traffic,
@@ -224,29 +256,44 @@ def main():
               f"status={pinfo.status}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
-        import oracle as O  # CPU baseline leg only
+        from oracle import timing as OT  # CPU baseline leg only
         del ws
         torch.cuda.empty_cache()
-        Ao = O.Operator(prob.ndim, prob.nx, prob.ny, prob.nz, c=prob.c)
-        fh = f.cpu().numpy()
-        x0 = np.zeros(N)
-        tc0 = time.perf_counter()
-        xo, res = O.sgmres(Ao, fh, x0, args.s, args.m, 0.0, max_blocks=args.cpu_blocks,
-                           basis=0 if basis == S.MONOMIAL else 1)
-        tc1 = time.perf_counter()
-        sample_vp = vec_passes_gmres([args.cpu_blocks], args.s)
-        full_vp = vec_passes_gmres(blocks_per_cycle(last.iters, last.cycles, args.m), args.s)
-        per_vp = (tc1 - tc0) / sample_vp
-        out["cpu_baseline"] = {
-            "value": per_vp * full_vp, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle s-GMRES(m={args.m}, s={args.s}) on the same {args.n}^3 problem, "
-                      f"first {args.cpu_blocks} blocks in {tc1 - tc0:.1f} s on 1 thread, scaled by "
-                      f"algorithmic vector passes ({sample_vp} -> {full_vp}) of the GPU solve",
-            "measured_s": tc1 - tc0,
-        }
-        print(f"# cpu oracle sample: {tc1 - tc0:.1f} s for {args.cpu_blocks} blocks", file=sys.stderr,
-              flush=True)
+        out["cpu_baseline"] = cpu_baseline(OT, args, N, blocks_per_cycle(last.iters, last.cycles,
+                                                                          args.m),
+                                           0 if basis == S.MONOMIAL else 1)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(OT, args, N, gpu_cycles, basis):
+    """The FP64 oracle timed on the host cores, scaled to the benchmarked
+    solve by algorithmic vector passes x points (both legs stream far more
+    than the caches hold).  All cores: one full restart cycle (m blocks) of
+    the same method on the cpu_n^3 grid, OpenMP timing build.  One core:
+    the first cpu_blocks blocks on the benchmarked grid, plain build."""
+    cpu = OT.host_cpu()
+    full = vec_passes_gmres(gpu_cycles, args.s) * N
+    nc = args.cpu_n ** 3
+    allc = OT.time_sgmres(3, args.cpu_n, 50.0, args.s, args.m, args.m, basis, threads=cpu["cores"])
+    est_all = allc["seconds"] / (vec_passes_gmres([allc["blocks"]], args.s) * nc) * full
+    one = OT.time_sgmres(3, args.n, 50.0, args.s, args.m, args.cpu_blocks, basis, threads=1)
+    est_one = one["seconds"] / (vec_passes_gmres([one["blocks"]], args.s) * N) * full
+    print(f"# cpu oracle: {allc['seconds']:.1f} s for a {args.m}-block cycle at {args.cpu_n}^3 on "
+          f"{cpu['cores']} threads, {one['seconds']:.1f} s for {args.cpu_blocks} blocks at "
+          f"{args.n}^3 on 1 thread", file=sys.stderr, flush=True)
+    return {
+        "value": est_all, "unit": "s", "cores": cpu["cores"], "kind": "oracle",
+        "cpu_model": cpu["model"],
+        "sample": f"oracle s-GMRES(m={args.m}, s={args.s}), OpenMP timing build on all "
+                  f"{cpu['cores']} host threads: one full {args.m}-block restart cycle of the "
+                  f"{args.cpu_n}^3 problem in {allc['seconds']:.1f} s, scaled by algorithmic vector "
+                  f"passes x points to the GPU solve ({len(gpu_cycles)} cycles, "
+                  f"{sum(gpu_cycles)} blocks at {args.n}^3)",
+        "measured_s": allc["seconds"],
+        "single_core": {"value": est_one, "cores": 1, "measured_s": one["seconds"],
+                        "sample": f"plain oracle build, first {args.cpu_blocks} blocks of the "
+                                  f"{args.n}^3 solve on 1 thread, scaled the same way"},
+    }
 
 
 def _classes(S, infos, steps):
@@ -275,26 +322,35 @@ def bench_mixed3d(args):
     import torch
     from paper_2001_04886_amd import problems as PB
     from paper_2001_04886_amd import sstep as S
+    import numpy as np
+    import oracle as O
+    from oracle import timing as OT
     dev = torch.device("cuda:0")
     prob = PB.cube_3d(args.n, seed=0, gamma=50.0)
     A = S.Stencil.from_problem(prob)
-    xt = torch.from_numpy(prob.x_true()).to(dev)
-    f = torch.empty_like(xt)
-    S.stencil_apply(A, xt, f)
+    Ao = O.Operator(prob.ndim, prob.nx, prob.ny, prob.nz, c=prob.c)
+    xt_h = prob.x_true()
+    f_h = O.apply(Ao, xt_h)   # right-hand side and residual checks by the FP64 oracle operator
+    xt = torch.from_numpy(xt_h).to(dev)
+    f = torch.from_numpy(f_h).to(dev)
     tol = 1e-10
     wsb = max(S.workspace_bytes(A, S.METHOD_GMRES, 12, args.m),
               S.workspace_bytes(A, S.METHOD_GMRES, 12, args.m, S.MIXED))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     x = torch.zeros_like(xt)
     res = {}
-    for name, s, prec, basis in [("fp64_s8", 8, S.FP64, S.MONOMIAL), ("mixed_s4", 4, S.MIXED, S.MONOMIAL),
-                                 ("mixed_s8", 8, S.MIXED, S.CHEBYSHEV),
-                                 ("mixed_s12", 12, S.MIXED, S.CHEBYSHEV),
-                                 # larger s in FP64: the three bases side by side
-                                 ("fp64_s12_monomial", 12, S.FP64, S.MONOMIAL),
-                                 ("fp64_s12_chebyshev", 12, S.FP64, S.CHEBYSHEV),
-                                 ("fp64_s12_newton", 12, S.FP64, S.NEWTON),
-                                 ("mixed_s12_newton", 12, S.MIXED, S.NEWTON)]:
+    configs = [("fp64_s8", 8, S.FP64, S.MONOMIAL),
+               # like with like: the FP64 solve in the basis the mixed s = 8 solve uses
+               ("fp64_s8_chebyshev", 8, S.FP64, S.CHEBYSHEV),
+               ("mixed_s4", 4, S.MIXED, S.MONOMIAL),
+               ("mixed_s8", 8, S.MIXED, S.CHEBYSHEV),
+               ("mixed_s12", 12, S.MIXED, S.CHEBYSHEV),
+               # larger s in FP64: the three bases side by side
+               ("fp64_s12_monomial", 12, S.FP64, S.MONOMIAL),
+               ("fp64_s12_chebyshev", 12, S.FP64, S.CHEBYSHEV),
+               ("fp64_s12_newton", 12, S.FP64, S.NEWTON),
+               ("mixed_s12_newton", 12, S.MIXED, S.NEWTON)]
+    for name, s, prec, basis in configs:
         infos = []
         for rep in range(args.warmup + args.steps):
             x.zero_()
@@ -308,13 +364,37 @@ def bench_mixed3d(args):
         t = sum(a for a, _ in infos) / len(infos)
         info = infos[-1][1]
         xerr = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+        xh = x.cpu().numpy()
+        r_or = float(np.linalg.norm(f_h - O.apply(Ao, xh)) / np.linalg.norm(f_h))
         res[name] = {"s": t, "blocks": info.iters, "cycles": info.cycles, "status": info.status,
                      "rel_resid": info.rel_resid, "x_err_vs_true": xerr,
+                     "oracle_true_rel_resid": r_or,
                      "basis": {S.MONOMIAL: "monomial", S.CHEBYSHEV: "chebyshev",
                                S.NEWTON: "newton"}[basis],
                      "kernels": _classes(S, [i for _, i in infos], len(infos))}
         print(f"# {name}: {t:.3f} s blocks={info.iters} cycles={info.cycles} rel_resid={info.rel_resid:.2e}"
               f" x_err={xerr:.2e}", file=sys.stderr, flush=True)
+    # error against the FP64 oracle where it can finish: the oracle's solution
+    # of the same problem on 64^3 to 1e-12 (all host cores), every
+    # configuration solved on the GPU to 1e-10
+    small = PB.cube_3d(args.oracle_n, seed=0, gamma=50.0)
+    As = S.Stencil.from_problem(small)
+    Aso = O.Operator(small.ndim, small.nx, small.ny, small.nz, c=small.c)
+    fs_h = O.apply(Aso, small.x_true())
+    fs = torch.from_numpy(fs_h).to(dev)
+    xo, ores = OT.solve_sgmres(3, args.oracle_n, 50.0, 8, args.m, 1e-12, 0,
+                               threads=OT.host_cpu()["cores"])
+    errs = {}
+    for name, s, prec, basis in configs:
+        xs = torch.zeros(small.N, dtype=torch.float64, device=dev)
+        info = S.gmres_solve(As, fs, xs, s, args.m, tol, precision=prec, basis=basis)
+        xsh = xs.cpu().numpy()
+        errs[name] = {"x_err_vs_oracle": float(np.linalg.norm(xsh - xo) / np.linalg.norm(xo)),
+                      "oracle_true_rel_resid": float(np.linalg.norm(fs_h - O.apply(Aso, xsh))
+                                                     / np.linalg.norm(fs_h)),
+                      "status": info.status}
+        print(f"# {args.oracle_n}^3 {name}: |x - x_oracle|/|x_oracle| = "
+              f"{errs[name]['x_err_vs_oracle']:.2e}", file=sys.stderr, flush=True)
     v = res["mixed_s8"]["s"]
     upd = res["mixed_s8"]["kernels"]["update"]["GBs"] or 0.0
     _line("mixed-precision s-step GMRES time to 1e-10 rel. resid, 7-pt 256^3", v, "s", False, v * 1e3,
@@ -323,6 +403,9 @@ def bench_mixed3d(args):
           f"FP64 Gram/LS/refinement, tol 1e-10 (s=8 headline; s=4, 12, FP64 s=8 and FP64 s=12 "
           f"with monomial / Chebyshev / Newton bases alongside)",
           {"results": res, "speedup_vs_fp64": res["fp64_s8"]["s"] / v,
+           "speedup_vs_fp64_same_basis": res["fp64_s8_chebyshev"]["s"] / v,
+           "vs_oracle": {"grid": f"{args.oracle_n}^3", "oracle": f"FP64 s-GMRES(m={args.m}, s=8) "
+                         f"to 1e-12 ({ores['blocks']} blocks)", "results": errs},
            "roofline": {"bound": "hbm", "kernel": "update", "achieved": upd, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": upd / HBM_PEAK_GBS, "traffic": None}})
 

@@ -29,13 +29,27 @@ NEWTON = 2
 OK, NOT_CONVERGED, ERR_ARG, ERR_BREAKDOWN, ERR_NONFINITE, ERR_NOMEM = 0, 1, -1, -2, -3, -5
 
 
+_FLAGS = ["-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-fPIC", "-shared"]
+LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
 def build() -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-Wall",
-           "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction).
+    Its OpenMP pragmas are ignored: one thread, sums in index order."""
+    cmd = ["gcc", *_FLAGS, "-Wno-unknown-pragmas", "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def build_omp() -> str:
+    """The same source compiled with -fopenmp (timing build for the CPU
+    baseline): N-length loops on all host cores, inner products summed in
+    fixed blocks.  Load it in a separate process (SSTEP_ORACLE_LIB)."""
+    cmd = ["gcc", *_FLAGS, "-fopenmp", "-o", LIB_OMP + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_OMP + ".tmp", LIB_OMP)
+    return LIB_OMP
 
 
 class _Stencil(C.Structure):

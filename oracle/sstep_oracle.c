@@ -47,8 +47,34 @@
 /* small dense helpers (plain loops)                                         */
 /* ------------------------------------------------------------------------ */
 
+/* Timing build only (compiled with -fopenmp, see build_omp in oracle/__init__.py):
+ * the N-length loops below run on all host cores; inner products are then
+ * summed in fixed blocks of ORC_OMP_BLOCK points whose sums are added in
+ * order, so the result does not depend on the thread count.  The plain
+ * build (no -fopenmp) ignores every pragma and sums in index order. */
+#define ORC_OMP_BLOCK 32768LL
+
 static double dot(long long n, const double *a, const double *b)
 {
+#ifdef _OPENMP
+    if (n > ORC_OMP_BLOCK) {
+        const long long nb = (n + ORC_OMP_BLOCK - 1) / ORC_OMP_BLOCK;
+        double *part = malloc(sizeof(double) * nb);
+        if (part) {
+#pragma omp parallel for schedule(static)
+            for (long long k = 0; k < nb; ++k) {
+                const long long p1 = (k + 1) * ORC_OMP_BLOCK < n ? (k + 1) * ORC_OMP_BLOCK : n;
+                double t = 0.0;
+                for (long long p = k * ORC_OMP_BLOCK; p < p1; ++p) t += a[p] * b[p];
+                part[k] = t;
+            }
+            double s = 0.0;
+            for (long long k = 0; k < nb; ++k) s += part[k];
+            free(part);
+            return s;
+        }
+    }
+#endif
     double s = 0.0;
     for (long long p = 0; p < n; ++p) s += a[p] * b[p];
     return s;
@@ -58,6 +84,7 @@ static double nrm2(long long n, const double *a) { return sqrt(dot(n, a, a)); }
 
 static void axpy(long long n, double alpha, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static) if (n > ORC_OMP_BLOCK)
     for (long long p = 0; p < n; ++p) y[p] += alpha * x[p];
 }
 
@@ -161,6 +188,7 @@ void orc_apply(const orc_stencil *A, const double *x, double *y)
         orc_ilu0_solve(A, A->ilu, x, t);
         x = t;
     }
+#pragma omp parallel for collapse(2) schedule(static) if (N > ORC_OMP_BLOCK)
     for (int l = 0; l < nz; ++l)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -279,16 +307,20 @@ void orc_mpk(const orc_stencil *A, const double *y0, int s, int basis, double si
         const double *yp = Y + (long long)(j - 1) * N;
         orc_apply(A, yp, yj);
         if (basis == ORC_BASIS_NEWTON) {
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
             for (long long p = 0; p < N; ++p) yj[p] = (yj[p] - th[j - 1] * yp[p]) / cd;
         } else if (basis == ORC_BASIS_CHEBYSHEV) {
             if (j == 1) {
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
                 for (long long p = 0; p < N; ++p) yj[p] = (yj[p] - cc * yp[p]) / cd;
             } else {
                 const double *ypp = Y + (long long)(j - 2) * N;
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
                 for (long long p = 0; p < N; ++p)
                     yj[p] = 2.0 * (yj[p] - cc * yp[p]) / cd - ypp[p];
             }
         } else {
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
             for (long long p = 0; p < N; ++p) yj[p] /= sigma;
         }
     }
@@ -324,6 +356,7 @@ static double true_residual(const orc_stencil *A, const double *f, const double 
 {
     const long long N = orc_size(A);
     orc_apply(A, x, r);
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
     for (long long p = 0; p < N; ++p) r[p] = f[p] - r[p];
     return nrm2(N, r);
 }
@@ -767,6 +800,7 @@ static int sgmres_cycle(const orc_stencil *A, double *x, int s, int m,
         free(Wf); free(Ls);
         return ORC_ERR_NOMEM;
     }
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
     for (long long p = 0; p < N; ++p) V[p] = work_r[p] / beta; /* w_1 = r_0 / beta */
     rhs[0] = beta;
     int ncols = 0, nb = 0, stop = 0;
@@ -820,6 +854,7 @@ static int sgmres_cycle(const orc_stencil *A, double *x, int s, int m,
             nu = nrm2(N, w);
             if (nu <= ORC_LUCKY_TOL * sqrt(Wk[s + s * (s + 1)])) lucky = 1;
             if (nu > 0.0)
+#pragma omp parallel for schedule(static) if (N > ORC_OMP_BLOCK)
                 for (long long p = 0; p < N; ++p) w[p] /= nu;
         } else {
             /* truncated block: column q depends on columns 0..q-1 numerically;

@@ -218,15 +218,34 @@ def _ptr(t) -> int:
         raise TypeError("expected a torch tensor")
     if not t.is_cuda:
         raise ValueError("tensor must live on the GPU")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"tensor lives on {t.device}, the current device is "
+                         f"cuda:{torch.cuda.current_device()}")
     if t.dim() > 0 and t.stride(-1) != 1:
         raise ValueError("tensor rows must be contiguous")
     return t.data_ptr()
 
 
 def _f64(t, n, name):
+    """Device address of a dense float64 array of at least n elements (the C
+    side reads and writes n elements from it)."""
     import torch
-    if t.dtype != torch.float64 or t.numel() < n:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.numel() < n:
         raise ValueError(f"{name} must be a float64 tensor with >= {n} elements")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _ptr(t)
+
+
+def _rows(t, nrows, n, name):
+    """Device address of nrows float64 rows of n elements, rows t.stride(0)
+    apart (a block of columns of the tall-skinny matrices)."""
+    import torch
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.dim() != 2
+            or t.shape[0] < nrows or t.shape[1] < n or t.stride(1) != 1
+            or (nrows > 1 and t.stride(0) < n)):
+        raise ValueError(f"{name} must be a float64 (>= {nrows}, >= {n}) tensor with unit "
+                         f"column stride and row stride >= {n}")
     return _ptr(t)
 
 
@@ -287,8 +306,9 @@ def gmres_solve(A: Stencil, f, x, s: int, m: int, tol: float, **kw) -> Info:
     """s-step GMRES(m) (Sec. 4, Alg. 4.2); x (in: x0, out: solution) updated in place."""
     sc = A.c_struct()
     info = InfoC()
+    fp, xp = _f64(f, A.N, "f"), _f64(x, A.N, "x")
     o = options(**kw)
-    load().sstep_gmres_solve(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, m, tol,
+    load().sstep_gmres_solve(C.byref(sc), fp, xp, s, m, tol,
                              C.byref(o), C.byref(info))
     return Info.from_c(info)
 
@@ -301,8 +321,9 @@ def gmres_solve_noalloc(A: Stencil, f, x, s: int, m: int, tol: float, **kw) -> I
     allocation); x updated in place."""
     sc = A.c_struct()
     info = InfoC()
+    fp, xp = _f64(f, A.N, "f"), _f64(x, A.N, "x")
     o = options(**kw)
-    load().sstep_gmres_solve_noalloc(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, m, tol,
+    load().sstep_gmres_solve_noalloc(C.byref(sc), fp, xp, s, m, tol,
                                      C.byref(o), C.byref(info))
     return Info.from_c(info)
 
@@ -311,8 +332,9 @@ def omin_solve(A: Stencil, f, x, s: int, k: int, tol: float, **kw) -> Info:
     """s-step Orthomin(k) (Sec. 3, Alg. 3.1); x updated in place."""
     sc = A.c_struct()
     info = InfoC()
+    fp, xp = _f64(f, A.N, "f"), _f64(x, A.N, "x")
     o = options(**kw)
-    load().sstep_omin_solve(C.byref(sc), _f64(f, A.N, "f"), _f64(x, A.N, "x"), s, k, tol,
+    load().sstep_omin_solve(C.byref(sc), fp, xp, s, k, tol,
                             C.byref(o), C.byref(info))
     return Info.from_c(info)
 
@@ -330,7 +352,7 @@ def kernel_mpk(A: Stencil, Y, s: int, basis=MONOMIAL, in_scale=1.0, sigma=1.0, c
     sc = A.c_struct()
     if Y.dim() != 2 or Y.shape[0] < s + 1:
         raise ValueError("Y must be (s+1, ld)")
-    _check(load().sstep_kernel_mpk(C.byref(sc), _f64(Y, (s + 1) * A.N, "Y"), Y.stride(0), s, basis,
+    _check(load().sstep_kernel_mpk(C.byref(sc), _rows(Y, s + 1, A.N, "Y"), Y.stride(0), s, basis,
                                    in_scale, sigma, cheb_c, cheb_d, _stream(stream)), "kernel_mpk")
 
 
@@ -341,7 +363,7 @@ def kernel_gram(X, Z, G=None, stream=None):
     ncx, ncz, N = X.shape[0], Z.shape[0], X.shape[1]
     if G is None:
         G = torch.empty((ncx, ncz), dtype=torch.float64, device=X.device)
-    _check(load().sstep_kernel_gram(_f64(X, ncx * N, "X"), X.stride(0), ncx, _f64(Z, ncz * N, "Z"),
+    _check(load().sstep_kernel_gram(_rows(X, ncx, N, "X"), X.stride(0), ncx, _rows(Z, ncz, N, "Z"),
                                     Z.stride(0), ncz, N, _f64(G, ncx * ncz, "G"), _stream(stream)),
            "kernel_gram")
     return G
@@ -350,9 +372,9 @@ def kernel_gram(X, Z, G=None, stream=None):
 def kernel_update(X, Y, M, stream=None) -> None:
     """Y[l] += sum_c X[c] M[c, l] (X: (ncx, ld), Y: (ncy, ld), M: (ncx, ncy) float64, device)."""
     ncx, ncy, N = X.shape[0], Y.shape[0], Y.shape[1]
-    xp = _f64(X, ncx * N, "X") if ncx else None
+    xp = _rows(X, ncx, N, "X") if ncx else None
     mp = _f64(M, ncx * ncy, "M") if ncx else None
-    _check(load().sstep_kernel_update(xp, X.stride(0) if ncx else N, ncx, _f64(Y, ncy * N, "Y"),
+    _check(load().sstep_kernel_update(xp, X.stride(0) if ncx else N, ncx, _rows(Y, ncy, N, "Y"),
                                       Y.stride(0), ncy, mp, N, _stream(stream)), "kernel_update")
 
 
@@ -414,8 +436,10 @@ def batch_workspace_bytes(stencils, s, m, wgs_per_cu=0, team=0) -> int:
 
 def _f32(t, n, name):
     import torch
-    if t.dtype != torch.float32 or t.numel() < n:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.numel() < n:
         raise ValueError(f"{name} must be a float32 tensor with >= {n} elements")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
     return _ptr(t)
 
 

@@ -57,3 +57,17 @@ def test_vector_pass_model_is_additive_and_grows_with_the_basis():
     assert all(b - a == 2 * s for a, b in zip(d, d[1:]))
     assert bench.vec_passes_gmres([40, 40, 30], s) == sum(bench.vec_passes_gmres([n], s)
                                                           for n in (40, 40, 30))
+
+
+def test_flop_model_closed_forms():
+    # per cycle of m blocks on N points: the Gram and the update each contract
+    # (k-1)s basis columns with s columns for k = 2..m, 2 flops per
+    # multiply-add, i.e. m(m-1)s^2 N flops; matrix powers take 13 flops per
+    # point and power for the 7-point stencil, 9 for the 5-point one
+    s, m, N = 8, 40, 1000
+    fl = bench.flops_gmres([m], s, N, 3)
+    assert fl["gram"] == fl["update"] == m * (m - 1) * s * s * N
+    assert fl["mpk"] == 13 * s * m * N
+    assert bench.flops_gmres([m], s, N, 2)["mpk"] == 9 * s * m * N
+    two = bench.flops_gmres([m, 3], s, N, 3)
+    assert two["gram"] == fl["gram"] + 3 * 2 * s * s * N

@@ -168,3 +168,22 @@ def test_learned_model_parameters_layout():
         assert not p[off:off + n].any()
     params, out_scale, meta = LN.load_model()
     assert params.size == 19393 and out_scale > 0 and meta["samples"] > 0
+
+
+def test_binding_rejects_views_the_c_side_cannot_address():
+    # the C ABI reads N elements straight from the data pointer: a padded 2-D
+    # view or a strided 1-D view must be refused before anything is called
+    torch = pytest.importorskip("torch")
+    A = S.Stencil(2, 4, 4, 1, (4.0, -1, -1, -1, -1, 0, 0))
+    x = torch.zeros(16, dtype=torch.float64)
+    padded = torch.zeros((4, 8), dtype=torch.float64)[:, :4]
+    strided = torch.zeros(32, dtype=torch.float64)[::2]
+    for bad in (padded, strided):
+        with pytest.raises(ValueError, match="contiguous"):
+            S.gmres_solve(A, bad, x, 2, 2, 1e-8)
+    with pytest.raises(ValueError, match="float64"):
+        S.gmres_solve(A, torch.zeros(16, dtype=torch.float32), x, 2, 2, 1e-8)
+    # a block of columns may have a row stride, but not a short one
+    with pytest.raises(ValueError, match="row stride"):
+        S.kernel_gram(torch.zeros((2, 16), dtype=torch.float64).as_strided((2, 16), (8, 1)),
+                      torch.zeros((1, 16), dtype=torch.float64))
