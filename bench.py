@@ -60,11 +60,17 @@ def flops_gmres(blocks_per_cycle, s, N, ndim):
     return fl
 
 
+KERNEL_SOURCES = ("kernels.hpp", "launch.hpp", "mpk.hpp", "mpk3d.hpp", "gram_self.hpp")
+
+
 def kernel_source_hash():
-    import glob
+    """Hash of the sources that define the N-length kernels and their launch
+    shapes (a committed traffic record is valid only for these)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2001_04886_amd", "csrc", "kernels.hpp")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2001_04886_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kind):

@@ -165,6 +165,18 @@ __device__ __forceinline__ void load_pts(const T* __restrict__ p, T (&v)[PPT]) {
     }
 }
 template <typename T, int PPT>
+__device__ __forceinline__ void store_pts_nt(T* __restrict__ p, const T (&v)[PPT]) {
+    constexpr int E = 16 / sizeof(T);
+    typedef T vt __attribute__((ext_vector_type(E)));
+#pragma unroll
+    for (int q = 0; q < PPT / E; ++q) {
+        vt t;
+#pragma unroll
+        for (int e = 0; e < E; ++e) t[e] = v[q * E + e];
+        __builtin_nontemporal_store(t, reinterpret_cast<vt*>(p + q * E));
+    }
+}
+template <typename T, int PPT>
 __device__ __forceinline__ void store_pts(T* __restrict__ p, const T (&v)[PPT]) {
     constexpr int E = 16 / sizeof(T);
     typedef T vt __attribute__((ext_vector_type(E)));
@@ -343,18 +355,22 @@ static __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* _
 // columns of V: every thread reads all inputs of its points before writing.
 // n2 may come from device memory (n2_dev) so a launch can cover a column count
 // that is only known on the device.  Arithmetic in TA.  V is streamed with
-// non-temporal loads.  NORM: per-workgroup partial sum of out[:,0]^2 (FP64).
+// non-temporal loads and out written with non-temporal stores; consecutive
+// point ranges go to the same XCD.  NORM: per-workgroup partial sum of
+// out[:,0]^2 (FP64), indexed by point range.  UT threads per workgroup.
 // ---------------------------------------------------------------------------
-template <typename TV, typename TB, typename TO, typename TA, int NOUT, bool NORM>
-__global__ __launch_bounds__(kThreads) void k_update(
+template <typename TV, typename TB, typename TO, typename TA, int NOUT, bool NORM, int UT>
+__global__ __launch_bounds__(UT) void k_update(
     long long N, const TB* base, long long ldb, const TV* V, long long ldv, int n2,
     const int* __restrict__ n2_dev, const double* __restrict__ M, TO* out, long long ldo,
     double* __restrict__ part, const int* __restrict__ skip) {
     if (skip && *skip) return;
+    static_assert(!NORM || UT == kThreads, "the norm partials use the 4-wave block sum");
     constexpr int PA = 16 / sizeof(TV), PB = 16 / sizeof(TB), PO = 16 / sizeof(TO);
     constexpr int PPT = PA > PB ? (PA > PO ? PA : PO) : (PB > PO ? PB : PO);
     const int nc = n2_dev ? *n2_dev : n2;
-    const long long p = ((long long)blockIdx.x * kThreads + threadIdx.x) * PPT;
+    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const long long p = ((long long)b * UT + threadIdx.x) * PPT;
     double nrm = 0.0;
     if (p + PPT <= N) {
         TA acc[NOUT][PPT];
@@ -413,7 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_update(
             TO t[PPT];
 #pragma unroll
             for (int e = 0; e < PPT; ++e) t[e] = (TO)acc[l][e];
-            store_pts<TO, PPT>(out + l * ldo + p, t);
+            store_pts_nt<TO, PPT>(out + l * ldo + p, t);
         }
         if (NORM) {
 #pragma unroll
@@ -438,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_update(
         __shared__ double lds[4];
         double v1[1] = {nrm}, o[1];
         block_sum<1>(v1, lds, o);
-        if (threadIdx.x == 0) part[blockIdx.x] = o[0];
+        if (threadIdx.x == 0) part[b] = o[0];
     }
 }
 
