@@ -720,11 +720,20 @@ def bench_learned(args):
     ds = LN.generate(args.eval_samples, 5000, nstreams=1, log=log)
     res = LN.evaluate(params, out_scale, ds, factor, sweeps, log=log)
     summ = {}
-    for mode in ("zero", "cnn", "cnn_nofallback"):
+    for mode in LN.MODES:
         r = res[mode]
         summ[mode] = {"mean_s": float(r["seconds"].mean()), "mean_blocks": float(r["blocks"].mean()),
+                      "median_blocks": float(np.median(r["blocks"])),
                       "converged_all": bool(np.all(r["status"] == S.OK))}
     fb = float(res["fallback"].mean())
+    # what the network adds beyond the Jacobi sweeps its guess goes through
+    summ["network_share"] = {
+        "blocks_vs_zero": summ["cnn"]["mean_blocks"] / summ["zero"]["mean_blocks"],
+        "blocks_vs_jacobi_only": summ["cnn"]["mean_blocks"] / summ["jacobi"]["mean_blocks"],
+        "time_vs_zero": summ["cnn"]["mean_s"] / summ["zero"]["mean_s"],
+        "time_vs_jacobi_only": summ["cnn"]["mean_s"] / summ["jacobi"]["mean_s"],
+        "training_samples": int(meta.get("samples", 0)),
+        "training_symmetries": 8 if meta.get("augment", True) else 1}
     # the network's own speed: forward (inference) at batch 32 and one
     # training step, timed with events on the stream the kernels run on
     B, n = 32, LN.GRID

@@ -76,7 +76,7 @@ def stencil_for(logk_sample):
 
 
 def solve_all(logk, f, x, s=SOLVE_S, m=SOLVE_M, tol=SOLVE_TOL, nstreams=4, x0_fn=None,
-              log=_log):
+              log=_log, graph=False):
     """Solve every sample with s-step GMRES(m) on ``nstreams`` concurrent
     streams (one host thread each; the library waits on its own stream).
     x holds the initial guesses on entry (or x0_fn(i, A, stream) fills them)
@@ -104,7 +104,7 @@ def solve_all(logk, f, x, s=SOLVE_S, m=SOLVE_M, tol=SOLVE_TOL, nstreams=4, x0_fn
                     if x0_fn is not None:
                         x0_fn(i, A, st)
                     info = S.gmres_solve(A, f[i].reshape(-1), x[i].reshape(-1), s, m, tol,
-                                         workspace=ws, stream=st)
+                                         workspace=ws, stream=st, graph=graph)
                     secs[i] = time.perf_counter() - t0
                     blocks[i], status[i] = info.iters, info.status
                     del coef
@@ -127,15 +127,54 @@ def solve_all(logk, f, x, s=SOLVE_S, m=SOLVE_M, tol=SOLVE_TOL, nstreams=4, x0_fn
     return blocks, status, secs
 
 
-def generate(count, seed, n=GRID, nstreams=4, device="cuda:0", log=_log):
+def generate(count, seed, n=GRID, nstreams=4, device="cuda:0", log=_log, graph=False):
     """Training/evaluation samples: seeded fields and their s-step GMRES
-    solutions to the solver tolerance from x0 = 0."""
+    solutions to the solver tolerance from x0 = 0 (graph: restart cycles
+    replayed from a hipGraph, one launch per cycle instead of ~500)."""
     import torch
     t0 = time.perf_counter()
     logk, f = sample_inputs(count, seed, n, device)
     x = torch.zeros_like(f)
     log(f"generating {count} samples (seed {seed}) on {nstreams} streams")
-    blocks, status, secs = solve_all(logk, f, x, nstreams=nstreams, log=log)
+    blocks, status, secs = solve_all(logk, f, x, nstreams=nstreams, log=log, graph=graph)
+    bad = int(np.sum(status != S.OK))
+    log(f"generated {count} samples in {time.perf_counter() - t0:.1f} s; "
+        f"mean blocks {blocks.mean():.0f}; not converged {bad}")
+    return Dataset(logk, f, x, blocks, secs, seed)
+
+
+def generate_batched(count, seed, n=GRID, chunk=512, device="cuda:0", log=_log, threads=0,
+                     wgs_per_cu=0, team=0):
+    """generate() through the batched persistent solver: chunks of ``chunk``
+    systems solved together in one launch per chunk (sstep_batch_plan_*),
+    each to the solver tolerance from x0 = 0.  The per-sample seconds are the
+    chunk's wall time divided evenly."""
+    import torch
+    t0 = time.perf_counter()
+    logk, f = sample_inputs(count, seed, n, device)
+    x = torch.zeros_like(f)
+    blocks = np.zeros(count, dtype=np.int64)
+    status = np.zeros(count, dtype=np.int64)
+    secs = np.zeros(count)
+    log(f"generating {count} samples (seed {seed}) in batches of {chunk}")
+    for c0 in range(0, count, chunk):
+        c1 = min(count, c0 + chunk)
+        stc = [stencil_for(logk[i]) for i in range(c0, c1)]
+        tc = time.perf_counter()
+        plan = S.BatchPlan([a for a, _ in stc], [f[i].reshape(-1) for i in range(c0, c1)],
+                           [x[i].reshape(-1) for i in range(c0, c1)], SOLVE_S, SOLVE_M, SOLVE_TOL,
+                           graph=False, threads=threads, wgs_per_cu=wgs_per_cu, team=team)
+        try:
+            _, infos = plan.execute()
+        finally:
+            plan.close()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tc
+        for j, info in enumerate(infos):
+            blocks[c0 + j], status[c0 + j] = info.iters, info.status
+        secs[c0:c1] = dt / (c1 - c0)
+        del stc
+        log(f"  solved {c1}/{count} ({dt:.1f} s for {c1 - c0})")
     bad = int(np.sum(status != S.OK))
     log(f"generated {count} samples in {time.perf_counter() - t0:.1f} s; "
         f"mean blocks {blocks.mean():.0f}; not converged {bad}")
@@ -150,6 +189,30 @@ def coarsen(ds, factor):
     lk = S.grid_pool(ds.logk.double().contiguous(), factor).float().contiguous()
     return Dataset(lk, S.grid_pool(ds.f, factor), S.grid_pool(ds.x, factor), ds.blocks,
                    ds.seconds, ds.seed)
+
+
+def save_shard(path, ds, factor):
+    """Write the block-averaged samples of ``ds`` (the network's training data)
+    as float32 arrays, with the fine solves' block counts and seconds."""
+    c = coarsen(ds, factor)
+    np.savez(path, logk=c.logk.float().cpu().numpy(), f=c.f.float().cpu().numpy(),
+             x=c.x.float().cpu().numpy(), blocks=ds.blocks, seconds=ds.seconds,
+             meta=np.array(json.dumps({"seed": ds.seed, "factor": factor, "grid": int(ds.logk.shape[1])})))
+
+
+def load_shards(paths, device="cuda:0"):
+    """Concatenate shards written by save_shard into one (block-averaged)
+    Dataset on the device."""
+    import torch
+    parts = []
+    for p in paths:
+        with np.load(p, allow_pickle=False) as z:
+            parts.append({k: z[k] for k in ("logk", "f", "x", "blocks", "seconds")})
+    cat = {k: np.concatenate([q[k] for q in parts]) for k in parts[0]}
+    return Dataset(torch.tensor(cat["logk"], dtype=torch.float32, device=device).contiguous(),
+                   torch.tensor(cat["f"], dtype=torch.float64, device=device).contiguous(),
+                   torch.tensor(cat["x"], dtype=torch.float64, device=device).contiguous(),
+                   cat["blocks"], cat["seconds"], None)
 
 
 def out_scale_of(ds, nsamp=64):
@@ -246,44 +309,64 @@ def load_model(path=DEFAULT_MODEL):
         return z["params"].astype(np.float32), float(z["out_scale"]), meta
 
 
-def evaluate(params, out_scale, ds, factor=1, sweeps=0, nstreams=1, log=_log, modes=None):
-    """Solve every sample of ``ds`` from x0 = 0, from the network's guess
-    (block averages over ``factor`` cells, ``sweeps`` Jacobi sweeps) with the
-    fallback rule, and from the raw guess; returns per-sample blocks and wall
-    seconds (guess included) for each, and the fallback flags."""
+MODES = ("zero", "jacobi", "cnn", "cnn_nofallback")
+
+
+def evaluate(params, out_scale, ds, factor=1, sweeps=0, nstreams=1, log=_log, modes=None,
+             graph=False):
+    """Solve every sample of ``ds`` from x0 = 0 ("zero"); from x0 = 0
+    followed by the same ``sweeps`` damped Jacobi sweeps and fallback rule as
+    the guess ("jacobi": the guess path with an all-zero network, whose output
+    is 0 -- the ablation that isolates what the network itself adds); from the
+    network's guess (block averages over ``factor`` cells, ``sweeps`` Jacobi
+    sweeps) with the fallback rule ("cnn"); and from the raw guess
+    ("cnn_nofallback").  Returns per-sample blocks and wall seconds (guess
+    included) for each, and the fallback flags of "cnn" and "jacobi"."""
     import torch
     dev = ds.logk.device
     n = ds.logk.shape[1]
     pdev = torch.as_tensor(params, device=dev)
+    pzero = torch.zeros_like(pdev)
     count = len(ds)
     ws = [torch.empty(S.x0_coarse_workspace_bytes(n, n, factor), dtype=torch.uint8, device=dev)
           for _ in range(nstreams)]
     fallback = np.zeros(count, dtype=bool)
+    fallback_j = np.zeros(count, dtype=bool)
     res = {}
-    for mode in modes or ("zero", "cnn", "cnn_nofallback"):
+    for mode in modes or MODES:
         x = torch.zeros_like(ds.f)
 
         def x0_fn(i, A, st, mode=mode):
             if mode == "zero":
                 return
-            used = S.x0_predict_coarse(pdev, out_scale, factor, sweeps, A,
-                                       ds.logk[i].reshape(-1), ds.f[i].reshape(-1),
-                                       x[i].reshape(-1), use_fallback=(mode == "cnn"),
+            used = S.x0_predict_coarse(pzero if mode == "jacobi" else pdev, out_scale, factor,
+                                       sweeps, A, ds.logk[i].reshape(-1), ds.f[i].reshape(-1),
+                                       x[i].reshape(-1), use_fallback=(mode != "cnn_nofallback"),
                                        workspace=ws[i % nstreams], stream=st)
             if mode == "cnn":
                 fallback[i] = used
+            elif mode == "jacobi":
+                fallback_j[i] = used
 
         blocks, status, secs = solve_all(ds.logk, ds.f, x, nstreams=nstreams, x0_fn=x0_fn,
-                                         log=lambda *a: None)
+                                         log=lambda *a: None, graph=graph)
         res[mode] = {"blocks": blocks, "status": status, "seconds": secs}
         log(f"  eval {mode} (factor {factor}, sweeps {sweeps}): mean blocks {blocks.mean():.1f}, "
             f"mean time {secs.mean() * 1e3:.1f} ms, not converged {int(np.sum(status != S.OK))}")
     res["fallback"] = fallback
+    res["fallback_jacobi"] = fallback_j
     return res
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gen-shard", default=None,
+                    help="only generate --samples solved samples (seed --seed) and write their "
+                         "block averages to this .npz")
+    ap.add_argument("--shards", nargs="+", default=None,
+                    help="train on these shards (from --gen-shard) instead of generating")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay restart cycles from a hipGraph in the data solves")
     ap.add_argument("--samples", type=int, default=2560)
     ap.add_argument("--val", type=int, default=128)
     ap.add_argument("--eval", type=int, default=64)
@@ -302,26 +385,40 @@ def main(argv=None):
     S.load()
     dev = "cuda:0"
     torch.cuda.init()
-    train_ds = generate(args.samples, args.seed, nstreams=args.streams, device=dev)
-    val_ds = generate(args.val, args.seed + 1, nstreams=args.streams, device=dev)
-    data_mean_blocks = float(train_ds.blocks.mean())
-    data_seconds = float(train_ds.seconds.sum())
-    train_c, val_c = coarsen(train_ds, args.coarsen), coarsen(val_ds, args.coarsen)
-    del train_ds
+    if args.gen_shard:
+        ds = generate(args.samples, args.seed, nstreams=args.streams, device=dev, graph=args.graph)
+        save_shard(args.gen_shard, ds, args.coarsen)
+        _log(f"wrote {args.gen_shard}: {len(ds)} samples, mean blocks {ds.blocks.mean():.0f}, "
+             f"{ds.seconds.sum():.0f} solver-seconds")
+        return
+    if args.shards:
+        train_c = load_shards(args.shards, dev)
+        args.samples = len(train_c)
+        data_mean_blocks = float(train_c.blocks.mean())
+        data_seconds = float(train_c.seconds.sum())
+    else:
+        train_ds = generate(args.samples, args.seed, nstreams=args.streams, device=dev,
+                            graph=args.graph)
+        data_mean_blocks = float(train_ds.blocks.mean())
+        data_seconds = float(train_ds.seconds.sum())
+        train_c = coarsen(train_ds, args.coarsen)
+        del train_ds
+    val_ds = generate(args.val, args.seed + 1, nstreams=args.streams, device=dev, graph=args.graph)
+    val_c = coarsen(val_ds, args.coarsen)
     params, out_scale, hist, train_s, steps = train(train_c, args.epochs, args.batch, args.lr,
                                                     val=val_c)
     del train_c
-    ev_ds = generate(args.eval, args.seed + 2, nstreams=args.streams, device=dev)
+    ev_ds = generate(args.eval, args.seed + 2, nstreams=args.streams, device=dev, graph=args.graph)
     evals = {}
     zero = None
     for sw in args.sweeps:
         res = evaluate(params, out_scale, ev_ds, args.coarsen, sw,
-                       modes=("cnn", "cnn_nofallback") if zero else None)
+                       modes=("jacobi", "cnn", "cnn_nofallback") if zero else None)
         if zero is None:
             zero = res["zero"]
         evals[sw] = {m: {"mean_blocks": float(res[m]["blocks"].mean()),
                          "mean_ms": float(res[m]["seconds"].mean() * 1e3)}
-                     for m in ("cnn", "cnn_nofallback")}
+                     for m in ("jacobi", "cnn", "cnn_nofallback")}
         evals[sw]["fallback_rate"] = float(res["fallback"].mean())
     best = min(args.sweeps, key=lambda sw: evals[sw]["cnn"]["mean_ms"])
     summary = {"zero": {"mean_blocks": float(zero["blocks"].mean()),
@@ -331,6 +428,8 @@ def main(argv=None):
             "val": args.val, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
             "seed": args.seed, "steps": steps, "train_seconds": train_s, "history": hist,
             "data_mean_blocks": data_mean_blocks, "data_seconds": data_seconds,
+            "data": ("shards " + " ".join(os.path.basename(p) for p in args.shards)
+                     if args.shards else f"generated, seed {args.seed}"),
             "eval": summary}
     save_model(args.out, params, out_scale, meta)
     _log(f"saved {args.out} (out_scale {out_scale:.4e}, sweeps {best})")
