@@ -200,15 +200,21 @@ def save_shard(path, ds, factor):
              meta=np.array(json.dumps({"seed": ds.seed, "factor": factor, "grid": int(ds.logk.shape[1])})))
 
 
+MAX_BLOCKS = 10000  # the solver's default block cap: a sample that reached it did not converge
+
+
 def load_shards(paths, device="cuda:0"):
     """Concatenate shards written by save_shard into one (block-averaged)
-    Dataset on the device."""
+    Dataset on the device, leaving out samples whose solve reached the block
+    cap without converging."""
     import torch
     parts = []
     for p in paths:
         with np.load(p, allow_pickle=False) as z:
             parts.append({k: z[k] for k in ("logk", "f", "x", "blocks", "seconds")})
     cat = {k: np.concatenate([q[k] for q in parts]) for k in parts[0]}
+    keep = cat["blocks"] < MAX_BLOCKS
+    cat = {k: v[keep] for k, v in cat.items()}
     return Dataset(torch.tensor(cat["logk"], dtype=torch.float32, device=device).contiguous(),
                    torch.tensor(cat["f"], dtype=torch.float64, device=device).contiguous(),
                    torch.tensor(cat["x"], dtype=torch.float64, device=device).contiguous(),
