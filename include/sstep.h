@@ -269,7 +269,8 @@ size_t sstep_batch_workspace_bytes(int nsys, const sstep_stencil *A, int s, int 
 
 /* Create a plan for nsys independent systems A[i] x[i] = f[i] (restarted
  * s-step GMRES(m), Sec. 4, Alg. 4.2, FP64, monomial basis).
- *   A    : HOST array [nsys] of constant-coefficient stencils (coef == NULL)
+ *   A    : HOST array [nsys] of stencils, constant coefficients or per-point
+ *          ones (coef: DEVICE [7][N], valid for the life of the plan)
  *   f, x : HOST arrays [nsys] of DEVICE pointers (x: initial guess in, solution
  *          out at every execution; the pointers must stay valid for the plan)
  *   s    : 1..8;  m: s-blocks per cycle, m <= 128 and m*s <= 512

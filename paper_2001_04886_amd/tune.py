@@ -6,6 +6,13 @@ two executions of the captured graph each, the faster kept -- and the fastest
 is cached in a JSON table keyed by GPU architecture, batch signature (count,
 total unknowns, largest system), s and m.  The table lives next to this
 module (``tuned/batched.json``) unless a path is given.
+
+A batch with no entry of its own takes the shape of the nearest tuned batch
+of the same architecture, s and m: batches are compared by the share of their
+unknowns in each power-of-two size class of the systems (what decides which
+systems get teams and how the work spreads over the workgroups), plus the
+log-ratios of their counts and total unknowns; beyond a distance of
+``NEAREST_MAX`` there is no match and the library's defaults apply.
 """
 from __future__ import annotations
 
@@ -26,9 +33,49 @@ def _arch():
     return getattr(p, "gcnArchName", p.name).split(":")[0]
 
 
+NEAREST_MAX = 0.5
+
+
 def batch_key(stencils, s, m):
     sizes = [a.N for a in stencils]
     return f"{_arch()}|n{len(sizes)}|N{sum(sizes)}|max{max(sizes)}|s{s}|m{m}"
+
+
+def size_histogram(sizes):
+    """Share of the unknowns in each power-of-two size class (class k holds
+    systems of 2^k .. 2^(k+1) - 1 points)."""
+    tot = float(sum(sizes))
+    h = {}
+    for n in sizes:
+        k = max(0, int(n).bit_length() - 1)
+        h[k] = h.get(k, 0.0) + n / tot
+    return {str(k): v for k, v in sorted(h.items())}
+
+
+def signature(sizes, s, m, arch):
+    return {"arch": arch, "s": s, "m": m, "n": len(sizes), "N": int(sum(sizes)),
+            "hist": size_histogram(sizes)}
+
+
+def distance(a, b):
+    """Distance of two batch signatures (inf across architectures, s or m)."""
+    import math
+    if (a["arch"], a["s"], a["m"]) != (b["arch"], b["s"], b["m"]):
+        return math.inf
+    keys = set(a["hist"]) | set(b["hist"])
+    l1 = sum(abs(a["hist"].get(k, 0.0) - b["hist"].get(k, 0.0)) for k in keys)
+    return l1 + abs(math.log(a["n"] / b["n"])) + abs(math.log(a["N"] / b["N"]))
+
+
+def nearest(sig, cache):
+    """(distance, record) of the tuned entry nearest to ``sig``."""
+    best = (float("inf"), None)
+    for rec in cache.values():
+        if "sig" in rec and "team" in rec:
+            d = distance(sig, rec["sig"])
+            if d < best[0]:
+                best = (d, rec)
+    return best
 
 
 def load_cache(path=DEFAULT_CACHE):
@@ -40,9 +87,14 @@ def load_cache(path=DEFAULT_CACHE):
 
 
 def lookup(stencils, s, m, path=DEFAULT_CACHE):
-    rec = load_cache(path).get(batch_key(stencils, s, m))
+    """Launch shape tuned for this batch, else that of the nearest tuned batch
+    (within NEAREST_MAX), else None."""
+    cache = load_cache(path)
+    rec = cache.get(batch_key(stencils, s, m))
     if not rec or "team" not in rec:
-        return None
+        d, rec = nearest(signature([a.N for a in stencils], s, m, _arch()), cache)
+        if rec is None or d > NEAREST_MAX:
+            return None
     return rec["threads"], rec["wgs_per_cu"], rec["team"]
 
 
@@ -74,7 +126,8 @@ def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAUL
     threads, wpc, team = (int(v) for v in key.split("x"))
     cache = load_cache(path)
     cache[batch_key(stencils, s, m)] = {"threads": threads, "wgs_per_cu": wpc, "team": team,
-                                        "ms": {k: v * 1e3 for k, v in times.items()}}
+                                        "ms": {k: v * 1e3 for k, v in times.items()},
+                                        "sig": signature([a.N for a in stencils], s, m, _arch())}
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
