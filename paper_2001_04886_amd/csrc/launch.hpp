@@ -419,12 +419,12 @@ inline bool mpk3_small_grid(const StencilView& v) {
     return tiles * ((v.nz + 2 * kMpk3L - 1) / (2 * kMpk3L)) < 128;
 }
 
-template <typename T, int L, int POS, int W, bool PREV, bool UNI>
+template <typename T, int L, int POS, int W, bool PREV, bool UNI, bool BETA, bool GAM>
 inline void mpk3_launch(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
                         const double* in_scale, const T* prev, const double* prev_scale,
                         const MpkLevels& lv, const int* skip) {
     using G = Mpk3Tile<L, POS, W>;
-    const auto kern = k_mpk3d<T, L, POS, W, PREV, UNI>;
+    const auto kern = k_mpk3d<T, L, POS, W, PREV, UNI, BETA, GAM>;
     const int ntx = (v.nx + G::IX - 1) / G::IX, nty = (v.ny + G::IY - 1) / G::IY;
     const long long tiles = (long long)ntx * nty;
     // chunks along z: minimise (rounds of resident workgroups) x (steps per
@@ -456,14 +456,23 @@ template <typename T, int L>
 inline void mpk3_go(Ctx& c, const StencilView& v, T* out0, long long ldo, const T* in,
                     const double* in_scale, const T* prev, const double* prev_scale,
                     const MpkLevels& lv, const int* skip) {
-    bool uni = true;
-    for (int j = 1; j < L; ++j) uni = uni && lv.alpha[j] == lv.alpha[0];
+    bool uni = true, beta = false, gam = false;
+    for (int j = 0; j < L; ++j) {
+        uni = uni && lv.alpha[j] == lv.alpha[0];
+        beta = beta || lv.beta[j] != 0.0;
+        gam = gam || lv.gam[j] != 0.0;
+    }
     const bool pv = prev != nullptr && lv.gam[0] != 0.0;
-    if (pv && !uni) throw HipFailure{hipErrorInvalidValue, "mpk3 level scales"};
     constexpr int WP = sizeof(T) == 8 ? 8 : 16;  // waves with y_{-1}
-    if (pv) mpk3_launch<T, L, 4, WP, true, true>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
-    else if (uni) mpk3_launch<T, L, 4, 16, false, true>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
-    else mpk3_launch<T, L, 4, 16, false, false>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip);
+#define SSTEP_MPK3(W_, PV, UN, BE, GA) \
+    mpk3_launch<T, L, 4, W_, PV, UN, BE, GA>(c, v, out0, ldo, in, in_scale, prev, prev_scale, lv, skip)
+    if (pv && !uni) throw HipFailure{hipErrorInvalidValue, "mpk3 level scales"};
+    if (pv) SSTEP_MPK3(WP, true, true, true, true);                      // three-term, continued
+    else if (!beta && !gam && uni) SSTEP_MPK3(16, false, true, false, false);  // monomial
+    else if (!gam && uni) SSTEP_MPK3(16, false, true, true, false);            // Newton
+    else if (!gam) SSTEP_MPK3(16, false, false, true, false);  // two-term, scales differ
+    else SSTEP_MPK3(16, false, false, true, true);             // three-term, first pass
+#undef SSTEP_MPK3
 }
 
 // Level coefficients of the monomial / Chebyshev recurrence at global level

@@ -44,35 +44,32 @@ struct Mpk3Tile {
     static constexpr int THREADS = 64 * W;
 };
 
-// Value of the same register in lane l - 1 (lane 0: 0) / lane l + 1 (lane 63: 0).
-template <typename T>
-__device__ __forceinline__ T mpk3_lane_below(T v) {
+// Value of the same register in lane l - 1 / lane l + 1 (whole-wave DPP shift;
+// lanes 0 / 63, which have no source, receive 0 -- they are halo lanes, whose
+// value is never needed).
+template <int CTRL, typename T>
+__device__ __forceinline__ T mpk3_lane_shift(T v) {
     if constexpr (sizeof(T) == 8) {
         const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-        const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, 0x138, 0xf, 0xf, false);
-        const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), 0x138, 0xf, 0xf, false);
-        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+        const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+        const unsigned slo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, true);
+        const unsigned shi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, true);
+        return __builtin_bit_cast(T, ((unsigned long long)shi << 32) | slo);
     } else {
-        return __builtin_bit_cast(
-            T, __builtin_amdgcn_update_dpp(0u, __builtin_bit_cast(unsigned, v), 0x138, 0xf, 0xf, false));
+        const unsigned u = __builtin_bit_cast(unsigned, v);
+        return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(u, u, CTRL, 0xf, 0xf, true));
     }
 }
 template <typename T>
-__device__ __forceinline__ T mpk3_lane_above(T v) {
-    if constexpr (sizeof(T) == 8) {
-        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-        const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)b, 0x130, 0xf, 0xf, false);
-        const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
-        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
-    } else {
-        return __builtin_bit_cast(
-            T, __builtin_amdgcn_update_dpp(0u, __builtin_bit_cast(unsigned, v), 0x130, 0xf, 0xf, false));
-    }
-}
+__device__ __forceinline__ T mpk3_lane_below(T v) { return mpk3_lane_shift<0x138>(v); }
+template <typename T>
+__device__ __forceinline__ T mpk3_lane_above(T v) { return mpk3_lane_shift<0x130>(v); }
 
 // PREV: the first level reads y_{-1} (three-term recurrence continued from an
-// earlier pass).  UNI: every level has the same alpha.
-template <typename T, int L, int POS, int W, bool PREV, bool UNI>
+// earlier pass).  UNI: every level has the same alpha.  BETA / GAM: some level
+// has a beta / gamma term (without them the terms are not compiled in: the
+// monomial basis has neither, the Newton basis only beta).
+template <typename T, int L, int POS, int W, bool PREV, bool UNI, bool BETA, bool GAM>
 __global__ __launch_bounds__(64 * W) void k_mpk3d(
     StencilView A, T* __restrict__ out0, long long ldo, const T* __restrict__ in,
     const double* __restrict__ in_scale, const T* __restrict__ prev,
@@ -216,8 +213,8 @@ __global__ __launch_bounds__(64 * W) void k_mpk3d(
                 T v;
                 if constexpr (UNI) v = arow[r] * acc;
                 else v = (T)lv.alpha[j - 1] * acc;
-                if (lv.beta[j - 1] != 0.0) v += (T)lv.beta[j - 1] * ctr;
-                if (lv.gam[j - 1] != 0.0) {
+                if constexpr (BETA) v += (T)lv.beta[j - 1] * ctr;
+                if constexpr (GAM) {
                     if (j >= 2) v += (T)lv.gam[j - 1] * ring[j >= 2 ? j - 2 : 0][P0][r];
                     else if constexpr (PREV) v += (T)lv.gam[j - 1] * pv1[r];
                 }
