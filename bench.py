@@ -636,10 +636,10 @@ def bench_batched(args):
     if shape is None or args.retune:
         shape = TU.tune_batched(st, fs, xs, s, m, tol,
                                 log=lambda msg: print(msg, file=sys.stderr, flush=True))
-    threads, wpc, team = shape
+    threads, wpc, team, gcols = shape
     ws = torch.empty(S.batch_workspace_bytes(st, s, m, wpc, team), dtype=torch.uint8, device=dev)
     plan = S.BatchPlan(st, fs, xs, s, m, tol, threads=threads, wgs_per_cu=wpc, graph=True,
-                       workspace=ws, team=team)
+                       workspace=ws, team=team, gram_cols=gcols)
     times = []
     for rep in range(args.warmup + args.steps):
         for x in xs:
@@ -670,12 +670,14 @@ def bench_batched(args):
           "f64", f"{len(st)} independent 2-D 5-pt convection-diffusion systems, side ~ U{{32..512}}, "
           f"gamma ~ U(0,100), s-GMRES(m={m}, s={s}), FP64, tol 1e-8, one persistent launch from a "
           f"captured hipGraph, autotuned shape {threads} threads x {wpc} WG/CU, teams of {team} "
-          f"workgroups on systems >= {team * 16384} points",
+          f"workgroups on systems >= {team * 16384} points, Gram tile "
+          f"{gcols or (4 if s <= 4 else 2)} columns per wave",
           {"converged_all": ok, "total_unknowns": int(sum(a.N for a in st)),
            "total_blocks": int(sum(i.iters for i in infos)), "max_x_err_vs_true": xerr,
            "algorithmic_GBs": gbs, "sequential_s": tseq,
            "speedup_vs_sequential": (tseq / t) if tseq else None,
-           "shape": {"threads": threads, "wgs_per_cu": wpc, "team": team},
+           "shape": {"threads": threads, "wgs_per_cu": wpc, "team": team,
+                     "gram_cols": gcols or (4 if s <= 4 else 2)},
            "team_systems": int(sum(1 for i in infos if i.matvecs > 1)),
            "roofline": {"bound": "hbm", "kernel": "k_batched_gmres", "achieved": gbs,
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,

@@ -121,6 +121,10 @@ typedef struct {
        first use and replays it for every later cycle (fewer launch gaps on
        small grids); ignored with profile = 1 */
     int32_t graph;
+    /* batched solver only: stored-block columns each wave takes per pass of
+       the block Gram (the Gram's column tile): 0 = default (4 for s <= 4,
+       2 for s <= 8); s <= 4 accepts 2 or 4, s <= 8 accepts 1 or 2 */
+    int32_t batch_gram_cols;
 } sstep_options;
 
 /* kernel classes reported in sstep_info (index into the arrays below) */

@@ -12,10 +12,12 @@
 //     the assembly are separated by team barriers because the stencil reads
 //     rows of neighbouring members;
 //   * phase 2: every workgroup takes the next small system alone.
-// Team barriers are counters advanced with agent-scope release/acquire
-// atomics (the L2 of each XCD is written back / invalidated), with a bounded
-// spin: on a time-out the launch is aborted and the affected systems report
-// SSTEP_ERR_HIP.  The grid size is checked against the occupancy of the
+// Team barriers are counters advanced with atomics, with a bounded spin: on a
+// time-out the launch is aborted and the affected systems report
+// SSTEP_ERR_HIP.  Where the hardware reports one XCD for every member of a
+// team (the usual case) the members share an L2 and a barrier costs only the
+// wait for their stores and an L1 invalidation; otherwise it takes agent-scope
+// release/acquire (the L2 written back and invalidated).  The grid size is checked against the occupancy of the
 // kernel, so every member of a team is resident.
 //
 // Per block the arithmetic is the same as in gmres.hip (normalised start
@@ -73,7 +75,8 @@ struct BatchArgs {
     double rank_tol, lucky_tol;
     BatchSlot* slots;
     int* queue;              // [0] big-system queue, [1] small-system queue, [2] abort flag
-    unsigned* team_sync;     // per team 64 words: [0] barrier counter, [32] mailbox
+    unsigned* team_sync;     // per team 64 words: [0] barrier counter, [32] mailbox,
+                             // [40 + rank] XCD of each member plus one
     int team;                // workgroups per team (1: no phase 1)
     long long spin_limit;
 };
@@ -81,6 +84,7 @@ struct BatchArgs {
 // A workgroup's team (kept in LDS).  T == 1: the workgroup alone.
 struct Team {
     int T, rank, parity, failed;
+    int local;  // every member runs on the same XCD (one L2)
     unsigned target;
     unsigned* cnt;
     int* mailbox;
@@ -102,31 +106,62 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     return t;
 }
 
+// XCD (accelerator complex) the calling workgroup runs on.
+__device__ __forceinline__ unsigned xcd_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xfu;
+}
+
+// Thread 0 arrives at the team's counter and waits for every member (bounded).
+__device__ __forceinline__ void team_arrive_wait(Team& tm, int order) {
+    tm.target += tm.T;
+    if (order == __ATOMIC_RELEASE)
+        __hip_atomic_fetch_add(tm.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_fetch_add(tm.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    long long spins = 0;
+    while (__hip_atomic_load(tm.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tm.target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > tm.limit ||
+            __hip_atomic_load(tm.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            tm.failed = 1;
+            __hip_atomic_store(tm.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+    }
+}
+
 // Team barrier: every member's global writes before it are visible to every
 // member after it.  Returns false (and marks the team failed) on a time-out or
 // an abort raised elsewhere; later barriers then return at once.
+//   * members on one XCD share its L2, and the per-CU vector L1 is write-
+//     through: each wave waits until its stores are acknowledged (by the L2),
+//     and after the arrival of every member the CU's L1 is invalidated so
+//     later loads see the other members' lines;
+//   * otherwise agent-scope release / acquire (the L2 is written back and
+//     invalidated as well, since the XCDs' L2s are not coherent).
 __device__ bool team_barrier(Team& tm) {
     if (tm.T == 1) {
         __syncthreads();
         return true;
+    }
+    if (tm.local) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0 && !tm.failed) {
+            team_arrive_wait(tm, __ATOMIC_RELAXED);
+            asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+        }
+        __syncthreads();
+        return !tm.failed;
     }
     // every wave publishes its own stores (agent-scope release: wait for them
     // and write the XCD's L2 back); __syncthreads alone does not wait for them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0 && !tm.failed) {
-        tm.target += tm.T;
-        __hip_atomic_fetch_add(tm.cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        long long spins = 0;
-        while (__hip_atomic_load(tm.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tm.target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > tm.limit ||
-                __hip_atomic_load(tm.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                tm.failed = 1;
-                __hip_atomic_store(tm.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
+        team_arrive_wait(tm, __ATOMIC_RELEASE);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -243,12 +278,18 @@ struct Walker {
 // One stencil pass over points [P0, P1): out = sc * (A in), or with f given
 // r = f - A in into out; returns this thread's share of sum(out^2).
 // Neighbours are summed in the order -x, +x, -y, +y, -z, +z, then the centre
-// (outside the grid = Dirichlet 0).  The operator's scalars are copied to
-// registers first (the descriptor sits in LDS).
+// (outside the grid = Dirichlet 0).  A thread takes SU points per step (NT
+// apart) and issues the loads of all of them before the arithmetic, so SU
+// points' worth of loads are in flight per thread; a neighbour outside the
+// grid is read at the point itself (always valid) and enters with weight 0,
+// which leaves the sum bit-identical to skipping it.  The operator's scalars
+// are copied to registers first (the descriptor sits in LDS).
 template <int NT>
 __device__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
                              const double* f, long long P0, long long P1) {
-    const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz, ndim = Ad.ndim;
+    constexpr int SU = 4;
+    const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz;
+    const bool d3 = Ad.ndim == 3;
     const long long N = Ad.N, sy = nx, sz = (long long)nx * ny;
     const double* coef = Ad.coef;
     double c[7];
@@ -260,28 +301,61 @@ __device__ double wg_stencil(const StencilView& Ad, const double* in, double* ou
     const SSTEP_GLOBAL double* gc = (const SSTEP_GLOBAL double*)coef;
     Walker w(nx, ny, P0 + threadIdx.x, NT);
     double sq = 0.0;
-    for (long long p = P0 + threadIdx.x; p < P1; p += NT, w.next()) {
-        double cc[7];
-        if (coef) {
+    for (long long pb = P0 + threadIdx.x; pb < P1; pb += (long long)SU * NT) {
+        long long pp[SU];
+        unsigned in_grid[SU];  // bit q: neighbour q (1 -x, 2 +x, 3 -y, 4 +y, 5 -z, 6 +z) inside
 #pragma unroll
-            for (int q = 0; q < 7; ++q) cc[q] = (q < 2 * ndim + 1) ? gc[q * N + p] : 0.0;
-        } else {
+        for (int u = 0; u < SU; ++u) {
+            const long long p = pb + (long long)u * NT;
+            const bool ok = p < P1;
+            pp[u] = ok ? p : pb;
+            unsigned b = 0;
+            if (ok) {
+                b = (unsigned)(w.i > 0) << 1 | (unsigned)(w.i < nx - 1) << 2 |
+                    (unsigned)(w.j > 0) << 3 | (unsigned)(w.j < ny - 1) << 4 |
+                    (unsigned)(w.l > 0) << 5 | (unsigned)(w.l < nz - 1) << 6;
+            }
+            in_grid[u] = b;
+            w.next();
+        }
+        double v[SU][7], cc[SU][7], fv[SU];
 #pragma unroll
-            for (int q = 0; q < 7; ++q) cc[q] = c[q];
+        for (int u = 0; u < SU; ++u) {
+            const long long p = pp[u];
+            const unsigned b = in_grid[u];
+            v[u][0] = gin[p];
+            v[u][1] = gin[(b >> 1 & 1u) ? p - 1 : p];
+            v[u][2] = gin[(b >> 2 & 1u) ? p + 1 : p];
+            v[u][3] = gin[(b >> 3 & 1u) ? p - sy : p];
+            v[u][4] = gin[(b >> 4 & 1u) ? p + sy : p];
+            if (d3) {
+                v[u][5] = gin[(b >> 5 & 1u) ? p - sz : p];
+                v[u][6] = gin[(b >> 6 & 1u) ? p + sz : p];
+            } else {
+                v[u][5] = v[u][6] = 0.0;
+            }
+            if (coef) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) cc[u][q] = (q < 5 || d3) ? gc[q * N + p] : 0.0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) cc[u][q] = c[q];
+            }
+            fv[u] = f ? gf[p] : 0.0;
         }
-        double acc = 0.0;
-        if (w.i > 0) acc += cc[1] * gin[p - 1];
-        if (w.i < nx - 1) acc += cc[2] * gin[p + 1];
-        if (w.j > 0) acc += cc[3] * gin[p - sy];
-        if (w.j < ny - 1) acc += cc[4] * gin[p + sy];
-        if (ndim == 3) {
-            if (w.l > 0) acc += cc[5] * gin[p - sz];
-            if (w.l < nz - 1) acc += cc[6] * gin[p + sz];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const unsigned b = in_grid[u];
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 1; q < 7; ++q) acc = fma((b >> q & 1u) ? cc[u][q] : 0.0, v[u][q], acc);
+            acc = fma(cc[u][0], v[u][0], acc);
+            const double r = f ? fv[u] - acc : sc * acc;
+            if (pb + (long long)u * NT < P1) {
+                gout[pp[u]] = r;
+                sq += r * r;
+            }
         }
-        acc += cc[0] * gin[p];
-        const double v = f ? gf[p] - acc : sc * acc;
-        gout[p] = v;
-        sq += v * v;
     }
     return sq;
 }
@@ -289,7 +363,8 @@ __device__ double wg_stencil(const StencilView& Ad, const double* in, double* ou
 // Y[:, l] += sum_{c < nc} V[:, c] M[c * ldm + l] for l < nout <= NMAX (M in LDS)
 // over the points of R; returns this thread's share of ||Y[:, 0]||^2 after the
 // update when norm.  Threads own point pairs (16-byte loads); eight columns of
-// V are in flight per step; the sum over c runs in column order.  Lanes
+// V are loaded while the previous eight are summed; the sum over c runs in
+// column order.  Lanes
 // l >= nout compute on clamped (valid) columns and are never stored, so the
 // loops have no data-dependent branches.
 template <int NT, int NMAX>
@@ -304,12 +379,37 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
 #pragma unroll
         for (int l = 0; l < NMAX; ++l) a[l] = ld2(Y + lc[l] * ldy + p);
         int c = 0;
+        // software pipeline: the next eight columns load while these FMAs run
+        d2v vn[8];
+        if (8 <= nc) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vn[u] = ld2(V + (long long)u * ld + p);
+        }
         for (; c + 8 <= nc; c += 8) {
             d2v v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = ld2(V + (long long)(c + u) * ld + p);
+            for (int u = 0; u < 8; ++u) v[u] = vn[u];
+            if (c + 16 <= nc) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) vn[u] = ld2(V + (long long)(c + 8 + u) * ld + p);
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int l = 0; l < NMAX; ++l) {
+                    const double mm = lds(M + (c + u) * ldm + lc[l]);
+                    a[l].x = fma(v[u].x, mm, a[l].x);
+                    a[l].y = fma(v[u].y, mm, a[l].y);
+                }
+        }
+        // the last nc mod 8 columns: four at a time with their loads issued
+        // together, then one at a time, summed in column order
+        for (; c + 4 <= nc; c += 4) {
+            d2v v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = ld2(V + (long long)(c + u) * ld + p);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int l = 0; l < NMAX; ++l) {
                     const double mm = lds(M + (c + u) * ldm + lc[l]);
@@ -351,20 +451,26 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
 }
 
 // out[a * nz + j] = sum_{p in R} X[:, a][p] Z[:, j][p] (a < ncx, j < nz <= KZ).
-// The waves of the workgroup walk the same 128 points per step, wave w taking
-// CAW columns of X in the current pass (CAW = 4, or 2 for KZ > 5 to bound the
-// registers; CAW NT/64 columns per pass).  The step's Z tile (KZ columns x 64 lanes x 16 bytes) is loaded once
+// The waves of the workgroup walk the same 256 points per step, each lane two
+// point pairs 128 points apart, wave w taking CAW columns of X in the current
+// pass (CAW NT/64 columns per pass; CAW is chosen by the caller to cover the
+// columns of X with few passes within the register budget).  The step's Z tile (KZ columns x 128 pairs x 16 bytes) is loaded once
 // for the workgroup, two steps ahead, into a three-deep LDS ring (ztile: 3
-// tiles of KZ*64 + 1 pairs; the extra pair takes the loads of threads without a
-// tile slot), so Z is read once per pass rather than once per few columns of
-// X.  The step loop is unrolled by two with named register sets and every load
-// in it is unconditional (addresses past the range clamp to its last step).
+// tiles of KZ*128 + 1 pairs; the extra pair takes the loads of threads without
+// a tile slot), so Z is read once per pass rather than once per few columns of
+// X.  X is loaded one step ahead.  The step loop is unrolled by two with named
+// register sets and every load in it is unconditional (addresses past the
+// range clamp to its last step).  Each lane sums its pairs in point order.
 // Each wave reduces its own columns.  Columns past ncx / nz are clamped to
 // valid ones and their sums dropped.
-template <int NT, int KZ>
+template <int KZ>
+constexpr int gram_ztile_pairs() { return 3 * (KZ * 128 + 1); }
+
+template <int NT, int KZ, int CAW>
 __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z, long long ldz,
                         int nz, const Range& R, double* out /* [ncx][nz] */, d2v* ztile) {
-    constexpr int CAW = KZ <= 5 ? 4 : 2, STEP = 128, TS = KZ * 64 + 1, NSL = (KZ * 64 + NT - 1) / NT;
+    constexpr int STEP = 256, TP = KZ * 128, TS = TP + 1,
+                  NSL = (TP + NT - 1) / NT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     SSTEP_LDS d2v* zt = (SSTEP_LDS d2v*)ztile;
     const double* zq[NSL];
@@ -372,11 +478,11 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
 #pragma unroll
     for (int i = 0; i < NSL; ++i) {
         const int q = threadIdx.x + NT * i;
-        const bool slot = q < KZ * 64;
-        const int j0 = slot ? q / 64 : 0;
+        const bool slot = q < TP;
+        const int j0 = slot ? q / 128 : 0;
         const int j = j0 < nz ? j0 : nz - 1;
-        zq[i] = Z + (long long)j * ldz + (slot ? (q % 64) * 2 : 0);
-        zd[i] = slot ? q : KZ * 64;
+        zq[i] = Z + (long long)j * ldz + (slot ? (q % 128) * 2 : 0);
+        zd[i] = slot ? q : TP;
     }
     const long long nstep = (R.pb - R.pa) / STEP;
     auto at = [&](long long st) { return R.pa + (st < nstep ? st : nstep - 1) * STEP; };
@@ -394,35 +500,43 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
             // step st: issue X(st+1), Z(st+2); FMAs on X(st) and tile st mod 3;
             // store the Z loaded at step st-1 into tile (st+1) mod 3 (last read
             // at step st-2); barrier
-            auto half = [&](long long st, d2v (&xcur)[CAW], d2v (&xnext)[CAW], d2v (&zload)[NSL],
-                            const d2v (&zstore)[NSL]) {
+            auto half = [&](long long st, d2v (&xcur)[CAW][2], d2v (&xnext)[CAW][2],
+                            d2v (&zload)[NSL], const d2v (&zstore)[NSL]) {
                 const long long px = at(st + 1) + 2 * lane, pz = at(st + 2);
 #pragma unroll
-                for (int a = 0; a < CAW; ++a) xnext[a] = ld2(xc[a] + px);
+                for (int a = 0; a < CAW; ++a) {
+                    xnext[a][0] = ld2(xc[a] + px);
+                    xnext[a][1] = ld2(xc[a] + px + 128);
+                }
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) zload[i] = ld2(zq[i] + pz);
                 __builtin_amdgcn_sched_barrier(0);  // the loads go out before the FMAs
                 const SSTEP_LDS d2v* tile = zt + (int)(st % 3) * TS;
 #pragma unroll
                 for (int j = 0; j < KZ; ++j) {
-                    const d2v zv = tile[j * 64 + lane];
+                    const d2v z0 = tile[j * 128 + lane], z1 = tile[j * 128 + 64 + lane];
 #pragma unroll
-                    for (int a = 0; a < CAW; ++a)
-                        acc[a][j] = fma(xcur[a].y, zv.y, fma(xcur[a].x, zv.x, acc[a][j]));
+                    for (int a = 0; a < CAW; ++a) {
+                        acc[a][j] = fma(xcur[a][0].y, z0.y, fma(xcur[a][0].x, z0.x, acc[a][j]));
+                        acc[a][j] = fma(xcur[a][1].y, z1.y, fma(xcur[a][1].x, z1.x, acc[a][j]));
+                    }
                 }
                 SSTEP_LDS d2v* w = zt + (int)((st + 1) % 3) * TS;
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) w[zd[i]] = zstore[i];
                 __syncthreads();
             };
-            d2v xa[CAW], xb[CAW], za[NSL], zb[NSL];
+            d2v xa[CAW][2], xb[CAW][2], za[NSL], zb[NSL];
 #pragma unroll
             for (int i = 0; i < NSL; ++i) {
                 zt[zd[i]] = ld2(zq[i] + at(0));
                 zb[i] = ld2(zq[i] + at(1));
             }
 #pragma unroll
-            for (int a = 0; a < CAW; ++a) xa[a] = ld2(xc[a] + at(0) + 2 * lane);
+            for (int a = 0; a < CAW; ++a) {
+                xa[a][0] = ld2(xc[a] + at(0) + 2 * lane);
+                xa[a][1] = ld2(xc[a] + at(0) + 2 * lane + 128);
+            }
             __syncthreads();
             long long st = 0;
             for (; st + 2 <= nstep; st += 2) {
@@ -431,8 +545,9 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
             }
             if (st < nstep) half(st, xa, xb, za, zb);
         }
-        // pairs after the last whole step, then the (at most two) single points
-        for (long long p = R.pa + nstep * STEP + 2 * lane; p < R.pb; p += STEP) {
+        // pairs after the last whole step (one per lane per 128 points, in
+        // point order), then the (at most two) single points
+        for (long long p = R.pa + nstep * STEP + 2 * lane; p < R.pb; p += 128) {
             d2v x[CAW];
 #pragma unroll
             for (int a = 0; a < CAW; ++a) x[a] = ld2(xc[a] + p);
@@ -543,7 +658,7 @@ __device__ __noinline__ void scalar_ysolve(BatchSlot& W, int ncols, int s, int l
 // LDS state of a workgroup handed to the solve.
 struct WgShared {
     double* red;
-    d2v* ztile;  // Z tiles of the block Gram: 3 x ((KZ + 1) * 64 + 1) pairs
+    d2v* ztile;  // Z tiles of the block Gram: 3 x ((KZ + 1) * 128 + 1) pairs
     double* sh;
     double* lw;
     GramFactor* lf;
@@ -553,7 +668,7 @@ struct WgShared {
 };
 
 // The whole restarted s-step GMRES for one system, by a team (T >= 1).
-template <int NT, int CA, int KZ>
+template <int NT, int GC, int KZ>
 __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, const WgShared& L,
                           const StencilView& A, Team& tm) {
     const int s = args.s, m = args.m, K = m * s, ldg_ = K + 1, s1 = s + 1;
@@ -617,7 +732,8 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             if (kb > 0) {
                 // C = V_prev^T [y_1..y_s]
                 double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
-                wg_gram<NT, KZ>(V, ld, c0, Yk + ld, ld, s, R, gout, ztile);
+                // the stored blocks: many columns of X, GC per wave and pass
+                wg_gram<NT, KZ, GC>(V, ld, c0, Yk + ld, ld, s, R, gout, ztile);
                 if (tm.T > 1) team_combine<NT>(tm, W, c0 * s, W.C);
                 pc.lap(SSTEP_K_GRAM);
                 // T_i = W_i^{-1} C_i, update coefficients
@@ -643,7 +759,9 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             // block Gram of [w_k, y_1..y_s]
             {
                 double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
-                wg_gram<NT, KZ + 1>(Yk, ld, s1, Yk, ld, s1, R, gout, ztile);
+                // s + 1 columns of X: one pass with one (s + 1 <= NT / 64) or two per wave
+                constexpr int CB = (KZ + 1) <= NT / 64 ? 1 : 2;
+                wg_gram<NT, KZ + 1, CB>(Yk, ld, s1, Yk, ld, s1, R, gout, ztile);
                 if (tm.T > 1) team_combine<NT>(tm, W, s1 * s1, W.C);
             }
             pc.lap(SSTEP_K_GRAM);
@@ -742,10 +860,12 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
     __syncthreads();
 }
 
-template <int NT, int CA, int KZ>
+// NT threads per workgroup, GC stored-block columns per wave in the block
+// Gram, KZ = 4 (s <= 4) or 8 (s <= 8)
+template <int NT, int GC, int KZ>
 __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
     __shared__ double red[NT / 64];
-    __shared__ d2v ztile[3 * ((KZ + 1) * 64 + 1)];
+    __shared__ d2v ztile[gram_ztile_pairs<KZ + 1>()];
     __shared__ double sh[3 * kMaxS + 4];
     __shared__ double lw[kMaxS * kMaxS];
     __shared__ GramFactor lf;
@@ -780,12 +900,27 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
             tm.rank = k % T;
             tm.parity = 0;
             tm.failed = 0;
+            tm.local = 0;
             tm.target = 0;
             tm.cnt = args.team_sync + (size_t)id * 64;
             tm.mailbox = (int*)(args.team_sync + (size_t)id * 64 + 32);
             tm.abort = abort;
             tm.limit = args.spin_limit;
             for (int r = 0; r < T; ++r) tm.member[r] = args.slots + ((k / T) * T + r) * 8 + x;
+            // publish this member's XCD (words 40.. of the team's block)
+            __hip_atomic_store((int*)(tm.cnt + 40 + tm.rank), (int)xcd_id() + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        // the cheaper barrier only where the hardware reports one XCD for the
+        // whole team (the grouping by blockIdx.x mod 8 is the usual dispatch)
+        if (team_barrier(tm) && threadIdx.x == 0) {
+            int same = 1;
+            const int x0 = __hip_atomic_load((int*)(tm.cnt + 40), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int r = 1; r < tm.T; ++r)
+                same &= __hip_atomic_load((int*)(tm.cnt + 40 + r), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) == x0;
+            tm.local = same && x0 > 0;
         }
         __syncthreads();
         for (;;) {
@@ -802,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
             BatchSys& S = args.sys[args.order_big[k]];
             if (threadIdx.x == 0) sA = S.A;
             __syncthreads();
-            solve_sys<NT, CA, KZ>(args, S, W, L, sA, tm);
+            solve_sys<NT, GC, KZ>(args, S, W, L, sA, tm);
             if (tm.failed) break;
         }
         __syncthreads();
@@ -827,7 +962,7 @@ __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
         BatchSys& S = args.sys[args.order_small[k]];
         if (threadIdx.x == 0) sA = S.A;
         __syncthreads();
-        solve_sys<NT, CA, KZ>(args, S, W, L, sA, tm);
+        solve_sys<NT, GC, KZ>(args, S, W, L, sA, tm);
     }
 }
 
@@ -845,6 +980,7 @@ static __global__ void k_batch_reset(int* queue, unsigned* team_sync, int nwords
 // ---------------------------------------------------------------------------
 struct BatchPlan {
     int nsys = 0, s = 0, m = 0, threads = 512, wgs_per_cu = 1, nslots = 0, team = 1, nteam_words = 0;
+    int gram_cols = 0;  // 0: the default Gram column tile
     double tick_khz = 1e5;  // wall-clock rate of the device (kHz)
     hipStream_t st = nullptr;
     void* ws = nullptr;
@@ -856,41 +992,39 @@ struct BatchPlan {
     BatchArgs args{};
 };
 
-template <int NT, int CA, int KZ>
-static const void* batch_kernel() {
-    return reinterpret_cast<const void*>(&k_batched_gmres<NT, CA, KZ>);
+// Calls f(kernel) with the instance for (threads, s, Gram column tile);
+// gram_cols 0 = the default tile.
+template <typename F>
+static void with_batch_kernel(int threads, int s, int gram_cols, F&& f) {
+#define SSTEP_BK(NT, GC, KZ) f(reinterpret_cast<const void*>(&k_batched_gmres<NT, GC, KZ>))
+    if (s <= 4) {
+        const bool narrow = gram_cols == 2;
+        if (threads == 256) { if (narrow) SSTEP_BK(256, 2, 4); else SSTEP_BK(256, 4, 4); }
+        else if (threads == 512) { if (narrow) SSTEP_BK(512, 2, 4); else SSTEP_BK(512, 4, 4); }
+        else { if (narrow) SSTEP_BK(1024, 2, 4); else SSTEP_BK(1024, 4, 4); }
+    } else {
+        const bool narrow = gram_cols == 1;
+        if (threads == 256) { if (narrow) SSTEP_BK(256, 1, 8); else SSTEP_BK(256, 2, 8); }
+        else if (threads == 512) { if (narrow) SSTEP_BK(512, 1, 8); else SSTEP_BK(512, 2, 8); }
+        else { if (narrow) SSTEP_BK(1024, 1, 8); else SSTEP_BK(1024, 2, 8); }
+    }
+#undef SSTEP_BK
 }
 
-// kernel instance for (threads, s): s <= 4 uses 4-column Gram / update lanes,
-// s <= 8 eight
-static const void* batch_kernel_for(int threads, int s) {
-    if (s <= 4) {
-        if (threads == 256) return batch_kernel<256, 8, 4>();
-        if (threads == 512) return batch_kernel<512, 8, 4>();
-        return batch_kernel<1024, 4, 4>();
-    }
-    if (threads == 256) return batch_kernel<256, 4, 8>();
-    if (threads == 512) return batch_kernel<512, 4, 8>();
-    return batch_kernel<1024, 2, 8>();
+static const void* batch_kernel_for(int threads, int s, int gram_cols) {
+    const void* k = nullptr;
+    with_batch_kernel(threads, s, gram_cols, [&](const void* kern) { k = kern; });
+    return k;
 }
 
 static void batch_enqueue(const BatchPlan& P, hipStream_t s) {
     const int nw = std::max(P.nteam_words, 4);
     hipLaunchKernelGGL(k_batch_reset, dim3((nw + 255) / 256), dim3(256), 0, s, P.args.queue,
                        P.args.team_sync, P.nteam_words);
-    const dim3 g(P.nslots);
-#define SSTEP_BATCH(NT, CA, KZ) \
-    hipLaunchKernelGGL((k_batched_gmres<NT, CA, KZ>), g, dim3(NT), 0, s, P.args)
-    if (P.s <= 4) {
-        if (P.threads == 256) SSTEP_BATCH(256, 8, 4);
-        else if (P.threads == 512) SSTEP_BATCH(512, 8, 4);
-        else SSTEP_BATCH(1024, 4, 4);
-    } else {
-        if (P.threads == 256) SSTEP_BATCH(256, 4, 8);
-        else if (P.threads == 512) SSTEP_BATCH(512, 4, 8);
-        else SSTEP_BATCH(1024, 2, 8);
-    }
-#undef SSTEP_BATCH
+    BatchArgs args = P.args;
+    void* params[] = {&args};
+    const void* k = batch_kernel_for(P.threads, P.s, P.gram_cols);
+    SSTEP_HIP(hipLaunchKernel(k, dim3(P.nslots), dim3(P.threads), params, 0, s));
 }
 
 // slots: compute units x workgroups per CU (every workgroup resident); without
@@ -923,6 +1057,7 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
     P->threads = opt.batch_threads > 0 ? opt.batch_threads : 512;
     P->wgs_per_cu = opt.batch_wgs_per_cu > 0 ? opt.batch_wgs_per_cu : 1;
     P->team = opt.batch_team > 0 ? opt.batch_team : 1;
+    P->gram_cols = opt.batch_gram_cols;
     P->nslots = batched_slots(nsys, P->wgs_per_cu, P->team);
     P->st = (hipStream_t)opt.stream;
     {
@@ -936,7 +1071,7 @@ int batched_plan_create(void** out, int nsys, const sstep_stencil* A, const doub
     // teams need every workgroup resident and whole teams inside each XCD
     if (P->team > 1) {
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel_for(P->threads, s),
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel_for(P->threads, s, P->gram_cols),
                                                          P->threads, 0) != hipSuccess) {
             (void)hipGetLastError();
             occ = 0;

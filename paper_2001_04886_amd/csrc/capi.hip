@@ -400,6 +400,8 @@ static int batch_args_ok(int nsys, const sstep_stencil* A, const double* const* 
         if (opt->batch_team != 0 && opt->batch_team != 1 && opt->batch_team != 2 &&
             opt->batch_team != 4 && opt->batch_team != 8)
             return 0;
+        const int gc = opt->batch_gram_cols;
+        if (gc != 0 && !(s <= 4 ? (gc == 2 || gc == 4) : (gc == 1 || gc == 2))) return 0;
     }
     for (int i = 0; i < nsys; ++i) {
         if (!stencil_ok(&A[i]) || !f[i] || !x[i]) return 0;

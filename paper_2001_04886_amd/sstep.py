@@ -51,7 +51,7 @@ class OptionsC(C.Structure):
                 ("stream", C.c_void_p), ("batch_threads", C.c_int32),
                 ("batch_wgs_per_cu", C.c_int32), ("batch_graph", C.c_int32),
                 ("batch_team", C.c_int32), ("precond", C.c_int32), ("orth", C.c_int32),
-                ("graph", C.c_int32)]
+                ("graph", C.c_int32), ("batch_gram_cols", C.c_int32)]
 
 
 class InfoC(C.Structure):
@@ -258,7 +258,7 @@ def _stream(stream=None) -> int:
 def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.0, inner_tol=0.0,
             workspace=None, stream=None, batch_threads=0, batch_wgs_per_cu=0,
             batch_graph=False, batch_team=0, precond=PRECOND_NONE,
-            orth=ORTH_CHOL, graph=False) -> OptionsC:
+            orth=ORTH_CHOL, graph=False, batch_gram_cols=0) -> OptionsC:
     o = OptionsC()
     load().sstep_default_options(C.byref(o))
     o.max_iters = int(max_iters)
@@ -278,6 +278,7 @@ def options(max_iters=0, precision=FP64, basis=MONOMIAL, profile=False, sigma=0.
     o.precond = int(precond)
     o.orth = int(orth)
     o.graph = 1 if graph else 0
+    o.batch_gram_cols = int(batch_gram_cols)
     return o
 
 
@@ -385,7 +386,7 @@ class BatchPlan:
     solution at every execute(); reset it to the initial guess first)."""
 
     def __init__(self, stencils, fs, xs, s, m, tol, threads=0, wgs_per_cu=0, graph=True,
-                 max_iters=0, workspace=None, team=0):
+                 max_iters=0, workspace=None, team=0, gram_cols=0):
         n = len(stencils)
         if not (len(fs) == len(xs) == n):
             raise ValueError("stencils, fs and xs must have equal lengths")
@@ -395,7 +396,8 @@ class BatchPlan:
         self._x = (C.c_void_p * n)(*[_f64(x, a.N, "x") for x, a in zip(xs, stencils)])
         self._keep = (list(fs), list(xs), workspace)
         o = options(max_iters=max_iters, workspace=workspace, batch_threads=threads,
-                    batch_wgs_per_cu=wgs_per_cu, batch_graph=graph, batch_team=team)
+                    batch_wgs_per_cu=wgs_per_cu, batch_graph=graph, batch_team=team,
+                    batch_gram_cols=gram_cols)
         self._plan = C.c_void_p()
         _check(load().sstep_batch_plan_create(C.byref(self._plan), n, self._A, self._f, self._x,
                                               s, m, tol, C.byref(o)), "batch_plan_create")

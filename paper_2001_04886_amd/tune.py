@@ -1,7 +1,8 @@
 """Autotuner for the batched persistent solver's launch shape.
 
 Candidate shapes (threads per workgroup x resident workgroups per compute
-unit x workgroups per team on large systems) are timed on the actual batch --
+unit x workgroups per team on large systems x the block Gram's column tile,
+i.e. stored-block columns per wave and pass) are timed on the actual batch --
 two executions of the captured graph each, the faster kept -- and the fastest
 is cached in a JSON table keyed by GPU architecture, batch signature (count,
 total unknowns, largest system), s and m.  The table lives next to this
@@ -22,8 +23,19 @@ import time
 
 from . import sstep as S
 
-CANDIDATES = ((256, 2, 1), (512, 1, 1), (512, 1, 2), (512, 1, 4), (1024, 1, 1), (1024, 1, 2),
-              (1024, 1, 4))
+# (threads, workgroups per CU, team, Gram column tile); tile NARROW is half the
+# default one (2 instead of 4 columns per wave for s <= 4, 1 instead of 2 for
+# s <= 8), 0 the default
+NARROW = -1
+CANDIDATES = ((256, 2, 1, 0), (512, 1, 1, 0), (512, 1, 2, 0), (512, 1, 2, NARROW), (512, 1, 4, 0),
+              (512, 1, 4, NARROW), (1024, 1, 1, 0), (1024, 1, 2, 0), (1024, 1, 4, 0))
+
+
+def gram_cols(s, tile):
+    """The library's batch_gram_cols value of a candidate tile for this s."""
+    if tile == NARROW:
+        return 2 if s <= 4 else 1
+    return int(tile)
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "batched.json")
 
 
@@ -87,28 +99,31 @@ def load_cache(path=DEFAULT_CACHE):
 
 
 def lookup(stencils, s, m, path=DEFAULT_CACHE):
-    """Launch shape tuned for this batch, else that of the nearest tuned batch
-    (within NEAREST_MAX), else None."""
+    """Launch shape (threads, workgroups per CU, team, Gram column tile; tile 0
+    = the library default) tuned for this batch, else that of the nearest
+    tuned batch (within NEAREST_MAX), else None."""
     cache = load_cache(path)
     rec = cache.get(batch_key(stencils, s, m))
     if not rec or "team" not in rec:
         d, rec = nearest(signature([a.N for a in stencils], s, m, _arch()), cache)
         if rec is None or d > NEAREST_MAX:
             return None
-    return rec["threads"], rec["wgs_per_cu"], rec["team"]
+    return rec["threads"], rec["wgs_per_cu"], rec["team"], rec.get("gram_cols", 0)
 
 
 def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAULT_CACHE,
                  max_iters=0, log=None):
     """Time every candidate shape on this batch; returns (threads, wgs_per_cu,
-    team) of the fastest and records all timings in the cache."""
+    team, gram_cols) of the fastest and records all timings in the cache."""
     import torch
-    nb = max(S.batch_workspace_bytes(stencils, s, m, w, t) for _, w, t in candidates)
+    nb = max(S.batch_workspace_bytes(stencils, s, m, c[1], c[2]) for c in candidates)
     ws = torch.empty(nb, dtype=torch.uint8, device=xs[0].device)
     times = {}
-    for threads, wpc, team in candidates:
+    for threads, wpc, team, tile in candidates:
+        gc = gram_cols(s, tile)
         plan = S.BatchPlan(stencils, fs, xs, s, m, tol, threads=threads, wgs_per_cu=wpc,
-                           graph=True, max_iters=max_iters, workspace=ws, team=team)
+                           graph=True, max_iters=max_iters, workspace=ws, team=team,
+                           gram_cols=gc)
         best = None
         for _ in range(2):
             for x in xs:
@@ -119,17 +134,19 @@ def tune_batched(stencils, fs, xs, s, m, tol, candidates=CANDIDATES, path=DEFAUL
             t = time.perf_counter() - t0
             best = t if best is None else min(best, t)
         plan.close()
-        times[f"{threads}x{wpc}x{team}"] = best
+        times[f"{threads}x{wpc}x{team}x{gc}"] = best
         if log:
-            log(f"# tune batched: threads={threads} wgs/CU={wpc} team={team}: {best * 1e3:.1f} ms")
+            log(f"# tune batched: threads={threads} wgs/CU={wpc} team={team} gram cols={gc or 'default'}: "
+                f"{best * 1e3:.1f} ms")
     key = min(times, key=times.get)
-    threads, wpc, team = (int(v) for v in key.split("x"))
+    threads, wpc, team, gc = (int(v) for v in key.split("x"))
     cache = load_cache(path)
     cache[batch_key(stencils, s, m)] = {"threads": threads, "wgs_per_cu": wpc, "team": team,
+                                        "gram_cols": gc,
                                         "ms": {k: v * 1e3 for k, v in times.items()},
                                         "sig": signature([a.N for a in stencils], s, m, _arch())}
     os.makedirs(os.path.dirname(path), exist_ok=True)
     with open(path, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     del ws
-    return threads, wpc, team
+    return threads, wpc, team, gc

@@ -129,11 +129,14 @@ def test_batch_options_validated_without_launching():
     f = (C.c_void_p * 2)(0x1000, 0x2000)
     x = (C.c_void_p * 2)(0x3000, 0x4000)
     plan = C.c_void_p()
-    for field, bad in (("batch_team", 3), ("batch_threads", 300), ("batch_wgs_per_cu", 5)):
+    # Gram column tile: 2 or 4 for s <= 4, 1 or 2 for s <= 8
+    for field, bad, s in (("batch_team", 3, 4), ("batch_threads", 300, 4), ("batch_wgs_per_cu", 5, 4),
+                          ("batch_gram_cols", 1, 4), ("batch_gram_cols", 3, 4),
+                          ("batch_gram_cols", 4, 8)):
         o = S.OptionsC()
         lib.sstep_default_options(C.byref(o))
         setattr(o, field, bad)
-        assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, f, x, 4, 8, 1e-8, C.byref(o)) == S.ERR_ARG
+        assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, f, x, s, 8, 1e-8, C.byref(o)) == S.ERR_ARG
     o = S.OptionsC()
     lib.sstep_default_options(C.byref(o))
     assert lib.sstep_batch_plan_create(C.byref(plan), 2, A, f, x, 9, 8, 1e-8, C.byref(o)) == S.ERR_ARG
@@ -151,9 +154,14 @@ def test_tuner_table_lookup(tmp_path, monkeypatch):
     assert TU.lookup(st, 4, 30, path) is None
     key = TU.batch_key(st, 4, 30)
     assert key == "gfx950|n2|N2624|max1600|s4|m30"
+    # a record without the Gram column tile gives tile 0 (the library default)
     json.dump({key: {"threads": 512, "wgs_per_cu": 1, "team": 2}}, open(path, "w"))
-    assert TU.lookup(st, 4, 30, path) == (512, 1, 2)
+    assert TU.lookup(st, 4, 30, path) == (512, 1, 2, 0)
+    json.dump({key: {"threads": 512, "wgs_per_cu": 1, "team": 2, "gram_cols": 2}}, open(path, "w"))
+    assert TU.lookup(st, 4, 30, path) == (512, 1, 2, 2)
     assert TU.lookup(st, 8, 30, path) is None
+    assert TU.gram_cols(4, TU.NARROW) == 2 and TU.gram_cols(8, TU.NARROW) == 1
+    assert TU.gram_cols(4, 0) == 0
     # a record without the team size (older table layout) is not used
     json.dump({key: {"threads": 512, "wgs_per_cu": 1}}, open(path, "w"))
     assert TU.lookup(st, 4, 30, path) is None

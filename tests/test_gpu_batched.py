@@ -85,6 +85,36 @@ def test_batched_launch_shapes_agree(threads, wpc):
         assert rel(x, xo) <= 1e-7
 
 
+@pytest.mark.parametrize("s,gram_cols,team", [(4, 2, 1), (4, 2, 2), (4, 4, 2), (8, 1, 2), (8, 2, 1)])
+def test_batched_gram_column_tiles_match_oracle(s, gram_cols, team):
+    # every Gram column tile the tuner may pick, alone and in teams (the two
+    # large systems go to teams).  s = 4: a fixed number of blocks against the
+    # oracle's iterates; s = 8 (a monomial basis whose rounding spread exceeds
+    # 1e-8 at fixed work): converged, judged by the true residual and the
+    # oracle's block count
+    probs = [PB.convdiff(2, 263, 40.0, seed=1500), PB.convdiff(3, 51, 50.0, seed=1501),
+             PB.convdiff(2, 33, 10.0, seed=1502), PB.convdiff(2, 47, 70.0, seed=1503)]
+    fs = [O.apply(operator(p), p.x_true()) for p in probs]
+    if s == 4:
+        status, infos, xs = run_batch(probs, fs, 4, 5, 0.0, max_iters=8, threads=512, team=team,
+                                      gram_cols=gram_cols)
+        for p, f, x, info in zip(probs, fs, xs, infos):
+            xo, res = O.sgmres(operator(p), f, np.zeros(p.N), 4, 5, 0.0, max_blocks=8)
+            assert info.iters == res.iters == 8 and info.cycles == res.cycles
+            assert rel(x, xo) <= 1e-8, (p.nx, rel(x, xo))
+        assert infos[0].matvecs == team
+        return
+    status, infos, xs = run_batch(probs, fs, 8, 4, 1e-10, threads=512, team=team,
+                                  gram_cols=gram_cols)
+    assert status == S.OK and infos[0].matvecs == team
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        A = operator(p)
+        assert info.status == S.OK
+        assert np.linalg.norm(f - O.apply(A, x)) / np.linalg.norm(f) <= 1e-10 * (1 + 1e-6)
+        _, res = O.sgmres(A, f, np.zeros(p.N), 8, 4, 1e-10)
+        assert abs(info.iters - res.iters) <= max(2, res.iters // 10), (info.iters, res.iters)
+
+
 def test_batched_graph_replays_are_identical():
     probs, fs = make_batch(SIZES, GAMMAS, seed0=700)
     st = [S.Stencil.from_problem(p) for p in probs]

@@ -240,9 +240,9 @@ def test_batched_512_true_residuals():
     fs = [dev(f) for f in fh]
     xs = [torch.zeros(p.N, dtype=torch.float64, device=DEV) for p in probs]
     shape = TU.lookup(st, 4, 30)
-    threads, wpc, team = shape if shape is not None else (0, 0, 0)
+    threads, wpc, team, gcols = shape if shape is not None else (0, 0, 0, 0)
     plan = S.BatchPlan(st, fs, xs, 4, 30, 1e-8, threads=threads, wgs_per_cu=wpc, graph=True,
-                       team=team)
+                       team=team, gram_cols=gcols)
     try:
         status, infos = plan.execute()
     finally:
