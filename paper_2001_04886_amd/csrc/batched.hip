@@ -226,7 +226,15 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 // explicit address spaces: the basis, x and f live in global memory, the
 // update coefficients in LDS (generic pointers would compile to flat accesses)
 __device__ __forceinline__ d2v ld2(const double* p) { return *(const SSTEP_GLOBAL d2v*)p; }
+// streamed once (stored basis columns): non-temporal, so they do not push the
+// lines that are reused (Z tiles, stencil neighbours) out of the caches
+__device__ __forceinline__ d2v ld2nt(const double* p) {
+    return __builtin_nontemporal_load((const SSTEP_GLOBAL d2v*)p);
+}
 __device__ __forceinline__ void st2(double* p, d2v v) { *(SSTEP_GLOBAL d2v*)p = v; }
+__device__ __forceinline__ void st2nt(double* p, d2v v) {
+    __builtin_nontemporal_store(v, (SSTEP_GLOBAL d2v*)p);
+}
 __device__ __forceinline__ double ldg(const double* p) { return *(const SSTEP_GLOBAL double*)p; }
 __device__ __forceinline__ void stg(double* p, double v) { *(SSTEP_GLOBAL double*)p = v; }
 __device__ __forceinline__ double lds(const double* p) { return *(const SSTEP_LDS double*)p; }
@@ -377,13 +385,13 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
     for (long long p = R.pa + 2 * threadIdx.x; p < R.pb; p += 2 * NT) {
         d2v a[NMAX];
 #pragma unroll
-        for (int l = 0; l < NMAX; ++l) a[l] = ld2(Y + lc[l] * ldy + p);
+        for (int l = 0; l < NMAX; ++l) a[l] = ld2nt(Y + lc[l] * ldy + p);
         int c = 0;
         // software pipeline: the next eight columns load while these FMAs run
         d2v vn[8];
         if (8 <= nc) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) vn[u] = ld2(V + (long long)u * ld + p);
+            for (int u = 0; u < 8; ++u) vn[u] = ld2nt(V + (long long)u * ld + p);
         }
         for (; c + 8 <= nc; c += 8) {
             d2v v[8];
@@ -391,7 +399,7 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
             for (int u = 0; u < 8; ++u) v[u] = vn[u];
             if (c + 16 <= nc) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) vn[u] = ld2(V + (long long)(c + 8 + u) * ld + p);
+                for (int u = 0; u < 8; ++u) vn[u] = ld2nt(V + (long long)(c + 8 + u) * ld + p);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -407,7 +415,7 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
         for (; c + 4 <= nc; c += 4) {
             d2v v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ld2(V + (long long)(c + u) * ld + p);
+            for (int u = 0; u < 4; ++u) v[u] = ld2nt(V + (long long)(c + u) * ld + p);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -428,7 +436,7 @@ __device__ double wg_lincomb(const double* V, long long ld, int nc, const double
         }
 #pragma unroll
         for (int l = 0; l < NMAX; ++l)
-            if (l < nout) st2(Y + l * ldy + p, a[l]);
+            if (l < nout) st2nt(Y + l * ldy + p, a[l]);
         if (norm) nacc += a[0].x * a[0].x + a[0].y * a[0].y;
     }
     // the (at most two) single points of the range
@@ -505,8 +513,8 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
                 const long long px = at(st + 1) + 2 * lane, pz = at(st + 2);
 #pragma unroll
                 for (int a = 0; a < CAW; ++a) {
-                    xnext[a][0] = ld2(xc[a] + px);
-                    xnext[a][1] = ld2(xc[a] + px + 128);
+                    xnext[a][0] = ld2nt(xc[a] + px);
+                    xnext[a][1] = ld2nt(xc[a] + px + 128);
                 }
 #pragma unroll
                 for (int i = 0; i < NSL; ++i) zload[i] = ld2(zq[i] + pz);
@@ -534,8 +542,8 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
             }
 #pragma unroll
             for (int a = 0; a < CAW; ++a) {
-                xa[a][0] = ld2(xc[a] + at(0) + 2 * lane);
-                xa[a][1] = ld2(xc[a] + at(0) + 2 * lane + 128);
+                xa[a][0] = ld2nt(xc[a] + at(0) + 2 * lane);
+                xa[a][1] = ld2nt(xc[a] + at(0) + 2 * lane + 128);
             }
             __syncthreads();
             long long st = 0;
