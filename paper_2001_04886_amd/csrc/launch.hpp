@@ -52,8 +52,14 @@ inline StencilView make_view(const sstep_stencil& A) {
 }
 
 // Column stride of basis blocks: a multiple of 64 elements (256 bytes FP32,
-// 512 bytes FP64) so every column starts aligned for 16-byte vector access.
-inline long long col_stride(long long N) { return round_up(std::max(N, 1LL), 64); }
+// 512 bytes FP64) so every column starts aligned for 16-byte vector access,
+// plus 256 elements.  Without the extra elements a power-of-two grid (256^3:
+// 2^24 points) puts the same point of every column at addresses that agree in
+// their low 27 bits, and the block Gram's hundreds of concurrent column
+// streams crowd the same HBM channels: the Gram ran at 6.18 TB/s, with the
+// padding at 6.49 (a 2 KiB offset per column; 256 bytes gave 6.32, 4 KiB was
+// slower than none in the update).
+inline long long col_stride(long long N) { return round_up(std::max(N, 1LL), 64) + 256; }
 
 // One profiled launch: class, algorithmic bytes, the block of the restart
 // cycle it belongs to (-1: always executed), and the event index before it.

@@ -74,6 +74,10 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library {p} is missing: run __graft_entry__.build() first")
+    # device memory and streams come from torch: its HIP runtime must be the
+    # one the library binds to, so it is loaded first (the library loaded
+    # first would pull in a second runtime that does not know torch's memory)
+    import torch  # noqa: F401
     lib = C.CDLL(p)
     vp, dp, i32, i64 = C.c_void_p, C.c_double, C.c_int, C.c_int64
     sp, op_, ip = C.POINTER(StencilC), C.POINTER(OptionsC), C.POINTER(InfoC)
