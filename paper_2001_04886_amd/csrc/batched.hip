@@ -292,8 +292,125 @@ struct Walker {
 // grid is read at the point itself (always valid) and enters with weight 0,
 // which leaves the sum bit-identical to skipping it.  The operator's scalars
 // are copied to registers first (the descriptor sits in LDS).
+// Bits 1..6 of a grid point: its -x, +x, -y, +y, -z, +z neighbour lies inside.
+__device__ __forceinline__ unsigned grid_bits(int i, int j, int l, int nx, int ny, int nz) {
+    return (unsigned)(i > 0) << 1 | (unsigned)(i < nx - 1) << 2 | (unsigned)(j > 0) << 3 |
+           (unsigned)(j < ny - 1) << 4 | (unsigned)(l > 0) << 5 | (unsigned)(l < nz - 1) << 6;
+}
+
+// One stencil row of a point from its seven values (order -x, +x, -y, +y, -z,
+// +z, centre; neighbours outside the grid weighted 0).
+__device__ __forceinline__ double stencil_point(unsigned b, const double (&c)[7], double vxm,
+                                                double vxp, double vym, double vyp, double vzm,
+                                                double vzp, double vc) {
+    double acc = 0.0;
+    acc = fma((b >> 1 & 1u) ? c[1] : 0.0, vxm, acc);
+    acc = fma((b >> 2 & 1u) ? c[2] : 0.0, vxp, acc);
+    acc = fma((b >> 3 & 1u) ? c[3] : 0.0, vym, acc);
+    acc = fma((b >> 4 & 1u) ? c[4] : 0.0, vyp, acc);
+    acc = fma((b >> 5 & 1u) ? c[5] : 0.0, vzm, acc);
+    acc = fma((b >> 6 & 1u) ? c[6] : 0.0, vzp, acc);
+    return fma(c[0], vc, acc);
+}
+
+// Constant coefficients: the same pass over point pairs [R.pa, R.pb) (16-byte
+// centre loads and stores, SP pairs per thread and step, 2 NT points apart),
+// then the (at most two) single points at the ends of the range.  Each point's
+// arithmetic is the one of the general pass below.
+template <int NT, bool D3>
+__device__ __forceinline__ double wg_stencil_pairs(const StencilView& Ad, const double (&c)[7],
+                                                   const double* in, double* out, double sc,
+                                                   const double* f, const Range& R) {
+    constexpr int SP = 4;
+    const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz;
+    const long long sy = nx, sz = (long long)nx * ny;
+    const SSTEP_GLOBAL double* gin = (const SSTEP_GLOBAL double*)in;
+    const SSTEP_GLOBAL double* gf = (const SSTEP_GLOBAL double*)f;
+    double sq = 0.0;
+    Walker w(nx, ny, R.pa + 2 * (long long)threadIdx.x, 2 * NT);
+    for (long long q0 = R.pa + 2 * (long long)threadIdx.x; q0 < R.pb; q0 += 2LL * SP * NT) {
+        long long pp[SP];
+        unsigned m0[SP], m1[SP];  // grid bits of the pair's two points
+#pragma unroll
+        for (int u = 0; u < SP; ++u) {
+            const long long p = q0 + 2LL * u * NT;
+            const bool ok = p < R.pb;
+            pp[u] = ok ? p : q0;
+            unsigned a = 0, b = 0;
+            if (ok) {
+                int i1 = w.i + 1, j1 = w.j, l1 = w.l;
+                if (i1 == nx) {
+                    i1 = 0;
+                    if (++j1 == ny) {
+                        j1 = 0;
+                        ++l1;
+                    }
+                }
+                a = grid_bits(w.i, w.j, w.l, nx, ny, nz);
+                b = grid_bits(i1, j1, l1, nx, ny, nz);
+            }
+            m0[u] = a;
+            m1[u] = b;
+            w.next();
+        }
+        // every load of the SP pairs before any arithmetic; a neighbour outside
+        // the grid is read at its own point (valid) and weighted 0
+        d2v ctr[SP], fp[SP];
+        double xm[SP], xp[SP], y0m[SP], y0p[SP], y1m[SP], y1p[SP];
+        double z0m[D3 ? SP : 1], z0p[D3 ? SP : 1], z1m[D3 ? SP : 1], z1p[D3 ? SP : 1];
+#pragma unroll
+        for (int u = 0; u < SP; ++u) {
+            const long long p = pp[u];
+            const unsigned a = m0[u], b = m1[u];
+            ctr[u] = ld2(in + p);
+            xm[u] = gin[(a >> 1 & 1u) ? p - 1 : p];
+            xp[u] = gin[(b >> 2 & 1u) ? p + 2 : p + 1];
+            y0m[u] = gin[(a >> 3 & 1u) ? p - sy : p];
+            y0p[u] = gin[(a >> 4 & 1u) ? p + sy : p];
+            y1m[u] = gin[(b >> 3 & 1u) ? p + 1 - sy : p + 1];
+            y1p[u] = gin[(b >> 4 & 1u) ? p + 1 + sy : p + 1];
+            if constexpr (D3) {
+                z0m[u] = gin[(a >> 5 & 1u) ? p - sz : p];
+                z0p[u] = gin[(a >> 6 & 1u) ? p + sz : p];
+                z1m[u] = gin[(b >> 5 & 1u) ? p + 1 - sz : p + 1];
+                z1p[u] = gin[(b >> 6 & 1u) ? p + 1 + sz : p + 1];
+            }
+            if (f) fp[u] = ld2(f + p);
+        }
+#pragma unroll
+        for (int u = 0; u < SP; ++u) {
+            const unsigned a = m0[u], b = m1[u];
+            // +x of the first point is the second, -x of the second the first
+            double r0 = stencil_point(a, c, xm[u], ctr[u].y, y0m[u], y0p[u], D3 ? z0m[u] : 0.0,
+                                      D3 ? z0p[u] : 0.0, ctr[u].x);
+            double r1 = stencil_point(b, c, ctr[u].x, xp[u], y1m[u], y1p[u], D3 ? z1m[u] : 0.0,
+                                      D3 ? z1p[u] : 0.0, ctr[u].y);
+            r0 = f ? fp[u].x - r0 : sc * r0;
+            r1 = f ? fp[u].y - r1 : sc * r1;
+            if (q0 + 2LL * u * NT < R.pb) {
+                st2(out + pp[u], d2v{r0, r1});
+                sq += r0 * r0 + r1 * r1;
+            }
+        }
+    }
+    const long long pe = threadIdx.x == 0 ? R.e0 : (threadIdx.x == 1 ? R.e1 : -1);
+    if (pe >= 0) {
+        const long long rest = pe / nx;
+        const int i = (int)(pe - rest * nx), j = (int)(rest % ny), l = (int)(rest / ny);
+        const unsigned b = grid_bits(i, j, l, nx, ny, nz);
+        double r = stencil_point(b, c, gin[(b >> 1 & 1u) ? pe - 1 : pe], gin[(b >> 2 & 1u) ? pe + 1 : pe],
+                                 gin[(b >> 3 & 1u) ? pe - sy : pe], gin[(b >> 4 & 1u) ? pe + sy : pe],
+                                 D3 ? gin[(b >> 5 & 1u) ? pe - sz : pe] : 0.0,
+                                 D3 ? gin[(b >> 6 & 1u) ? pe + sz : pe] : 0.0, gin[pe]);
+        r = f ? gf[pe] - r : sc * r;
+        stg(out + pe, r);
+        sq += r * r;
+    }
+    return sq;
+}
+
 template <int NT>
-__device__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
+__device__ __noinline__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
                              const double* f, long long P0, long long P1) {
     constexpr int SU = 4;
     const int nx = Ad.nx, ny = Ad.ny, nz = Ad.nz;
@@ -303,6 +420,11 @@ __device__ double wg_stencil(const StencilView& Ad, const double* in, double* ou
     double c[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) c[q] = Ad.c[q];
+    if (!coef) {
+        const Range R(P0, P1);
+        return d3 ? wg_stencil_pairs<NT, true>(Ad, c, in, out, sc, f, R)
+                  : wg_stencil_pairs<NT, false>(Ad, c, in, out, sc, f, R);
+    }
     const SSTEP_GLOBAL double* gin = (const SSTEP_GLOBAL double*)in;
     SSTEP_GLOBAL double* gout = (SSTEP_GLOBAL double*)out;
     const SSTEP_GLOBAL double* gf = (const SSTEP_GLOBAL double*)f;
