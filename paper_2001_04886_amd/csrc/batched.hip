@@ -927,7 +927,21 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
                 else z = (l == q) ? nu : 0.0;
                 val = sigma * z;
                 if (r <= c0) {
-                    for (int cp = (r > 0 ? r - 1 : 0); cp < c0; ++cp) {
+                    // four steps' loads issued together (the G entries are read
+                    // whether or not their coefficient is 0; all lie inside G)
+                    int cp = r > 0 ? r - 1 : 0;
+                    for (; cp + 4 <= c0; cp += 4) {
+                        double tv[4], gv[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            tv[u] = W.T[(cp + u) * s1 + j];
+                            gv[u] = W.G[r + (cp + u) * ldg_];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (tv[u] != 0.0) val -= gv[u] * tv[u];
+                    }
+                    for (; cp < c0; ++cp) {
                         const double t = W.T[cp * s1 + j];
                         if (t != 0.0) val -= W.G[r + cp * ldg_] * t;
                     }
@@ -951,9 +965,28 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             }
             __syncthreads();
             if (tid < q) {
+                // the earlier rotations on the new columns, one thread per
+                // column; eight rotations' operands loaded together (each
+                // col[i + 1] is read before col[i + 1] is rewritten, as in the
+                // one-at-a-time order)
                 double* col = W.R + (c0 + tid) * ldg_;
                 double x0 = col[0];
-                for (int i = 0; i < c0; ++i) {
+                int i = 0;
+                for (; i + 8 <= c0; i += 8) {
+                    double cv[8], sv[8], xv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        cv[u] = W.cs[i + u];
+                        sv[u] = W.sn[i + u];
+                        xv[u] = col[i + u + 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        col[i + u] = cv[u] * x0 + sv[u] * xv[u];
+                        x0 = -sv[u] * x0 + cv[u] * xv[u];
+                    }
+                }
+                for (; i < c0; ++i) {
                     const double cth = W.cs[i], sth = W.sn[i], x1 = col[i + 1];
                     col[i] = cth * x0 + sth * x1;
                     x0 = -sth * x0 + cth * x1;
