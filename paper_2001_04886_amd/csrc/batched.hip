@@ -17,8 +17,9 @@
 // SSTEP_ERR_HIP.  Where the hardware reports one XCD for every member of a
 // team (the usual case) the members share an L2 and a barrier costs only the
 // wait for their stores and an L1 invalidation; otherwise it takes agent-scope
-// release/acquire (the L2 written back and invalidated).  The grid size is checked against the occupancy of the
-// kernel, so every member of a team is resident.
+// release/acquire (the L2 written back and invalidated).  The grid size is
+// checked against the occupancy of the kernel, so every member of a team is
+// resident.
 //
 // Per block the arithmetic is the same as in gmres.hip (normalised start
 // vectors with their norms folded into coefficients, one-pass block CGS, a
@@ -283,15 +284,6 @@ struct Walker {
     }
 };
 
-// One stencil pass over points [P0, P1): out = sc * (A in), or with f given
-// r = f - A in into out; returns this thread's share of sum(out^2).
-// Neighbours are summed in the order -x, +x, -y, +y, -z, +z, then the centre
-// (outside the grid = Dirichlet 0).  A thread takes SU points per step (NT
-// apart) and issues the loads of all of them before the arithmetic, so SU
-// points' worth of loads are in flight per thread; a neighbour outside the
-// grid is read at the point itself (always valid) and enters with weight 0,
-// which leaves the sum bit-identical to skipping it.  The operator's scalars
-// are copied to registers first (the descriptor sits in LDS).
 // Bits 1..6 of a grid point: its -x, +x, -y, +y, -z, +z neighbour lies inside.
 __device__ __forceinline__ unsigned grid_bits(int i, int j, int l, int nx, int ny, int nz) {
     return (unsigned)(i > 0) << 1 | (unsigned)(i < nx - 1) << 2 | (unsigned)(j > 0) << 3 |
@@ -409,6 +401,18 @@ __device__ __forceinline__ double wg_stencil_pairs(const StencilView& Ad, const 
     return sq;
 }
 
+// One stencil pass over points [P0, P1): out = sc * (A in), or with f given
+// r = f - A in into out; returns this thread's share of sum(out^2).
+// Neighbours are summed in the order -x, +x, -y, +y, -z, +z, then the centre
+// (outside the grid = Dirichlet 0).  Constant coefficients take the paired
+// pass above; per-point coefficients: a thread takes SU points per step (NT
+// apart) and issues the loads of all of them before the arithmetic, so SU
+// points' worth of loads are in flight per thread; a neighbour outside the
+// grid is read at the point itself (always valid) and enters with weight 0,
+// which leaves the sum bit-identical to skipping it.  The operator's scalars
+// are copied to registers first (the descriptor sits in LDS).  Out of line:
+// inlined, its registers pushed the solve's long-lived state into scratch
+// inside the Gram and update loops.
 template <int NT>
 __device__ __noinline__ double wg_stencil(const StencilView& Ad, const double* in, double* out, double sc,
                              const double* f, long long P0, long long P1) {
