@@ -123,7 +123,8 @@ typedef struct {
     int32_t graph;
     /* batched solver only: stored-block columns each wave takes per pass of
        the block Gram (the Gram's column tile): 0 = default (4 for s <= 4,
-       2 for s <= 8); s <= 4 accepts 2 or 4, s <= 8 accepts 1 or 2 */
+       2 for s <= 8); s <= 4 accepts 2 or 4, s <= 8 accepts 1 or 2, any
+       other value makes sstep_batch_plan_create return SSTEP_ERR_ARG */
     int32_t batch_gram_cols;
 } sstep_options;
 

@@ -36,6 +36,8 @@ def gram_cols(s, tile):
     if tile == NARROW:
         return 2 if s <= 4 else 1
     return int(tile)
+
+
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned", "batched.json")
 
 
