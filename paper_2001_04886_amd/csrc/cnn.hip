@@ -17,7 +17,9 @@
 //   * the two 32 -> 32 layers, forward and data-gradient, are implicit GEMMs on
 //     v_mfma_f32_16x16x32_bf16: M = 16 output channels, N = 16 points of a
 //     row, K = the 32 input channels of one tap, 9 taps accumulated; a wave
-//     keeps all its weights in registers and streams point groups;
+//     keeps all its weights in registers and walks rows group by group, the
+//     x-shifted taps formed by lane shifts from the neighbouring groups (3
+//     loads per group instead of 9);
 //   * their weight gradients contract over points: both operands are staged
 //     through LDS transposed (channel-major) so a lane reads 8 consecutive
 //     points of one channel, and the 9 taps are 9 MFMA accumulators;
@@ -158,24 +160,62 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(int B, int H, int W,
     for (int q = 0; q < 4; ++q) dst[q] = o[q];
 }
 
-// 32 -> 32 dilated 3x3 layer on MFMA.
+// Value of the same 32-bit register D lanes to the left / right within each
+// row of 16 lanes (lanes without a source in the row: don't care, the caller
+// selects another source for them).
+template <int D>
+__device__ __forceinline__ bf16x8 row_from_left(bf16x8 v) {
+    uint4 u = __builtin_bit_cast(uint4, v);
+    u.x = __builtin_amdgcn_update_dpp(u.x, u.x, 0x110 + D, 0xf, 0xf, false);
+    u.y = __builtin_amdgcn_update_dpp(u.y, u.y, 0x110 + D, 0xf, 0xf, false);
+    u.z = __builtin_amdgcn_update_dpp(u.z, u.z, 0x110 + D, 0xf, 0xf, false);
+    u.w = __builtin_amdgcn_update_dpp(u.w, u.w, 0x110 + D, 0xf, 0xf, false);
+    return __builtin_bit_cast(bf16x8, u);
+}
+template <int D>
+__device__ __forceinline__ bf16x8 row_from_right(bf16x8 v) {
+    uint4 u = __builtin_bit_cast(uint4, v);
+    u.x = __builtin_amdgcn_update_dpp(u.x, u.x, 0x100 + D, 0xf, 0xf, false);
+    u.y = __builtin_amdgcn_update_dpp(u.y, u.y, 0x100 + D, 0xf, 0xf, false);
+    u.z = __builtin_amdgcn_update_dpp(u.z, u.z, 0x100 + D, 0xf, 0xf, false);
+    u.w = __builtin_amdgcn_update_dpp(u.w, u.w, 0x100 + D, 0xf, 0xf, false);
+    return __builtin_bit_cast(bf16x8, u);
+}
+__device__ __forceinline__ bf16x8 sel8(bool c, bf16x8 a, bf16x8 b) {
+    const uint4 ua = __builtin_bit_cast(uint4, a), ub = __builtin_bit_cast(uint4, b);
+    uint4 r;
+    r.x = c ? ua.x : ub.x;
+    r.y = c ? ua.y : ub.y;
+    r.z = c ? ua.z : ub.z;
+    r.w = c ? ua.w : ub.w;
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// 32 -> 32 dilated 3x3 layer on MFMA, dilation D.
 //   forward  (DGRAD = false): Y[p][co] = relu(b[co] + sum_{tap,ci} W[co][ci][tap] X[p+off(tap)][ci])
 //   data gradient (DGRAD = true):
 //            Y[p][ci] = [mask[p][ci] > 0] * sum_{tap,co} W[co][ci][8-tap] X[p+off(tap)][co]
 //   (off(8 - tap) = -off(tap), so the adjoint is the same gather with the
 //   weights transposed and the taps reversed).
 // One wave computes 16 consecutive points of a row x 32 output channels per
-// step as two 16x16 MFMA tiles over 9 taps x 32 input channels.  The grid is
-// persistent (about two workgroups per CU): a workgroup stages the layer's
-// weights once, as bf16 in the MFMA lane order, through LDS; each wave then
-// streams point groups, the next group's nine gathers in flight while the
-// current group's 18 MFMAs run.
-template <bool DGRAD>
-__global__ __launch_bounds__(kThreads) void k_conv32(int B, int H, int W, int d,
+// step as two 16x16 MFMA tiles over 9 taps x 32 input channels: lane l holds
+// point l mod 16 of the group and input channels 8 (l / 16) .. +8.  The grid
+// is persistent (about two workgroups per CU): a workgroup stages the
+// layer's weights once, as bf16 in the MFMA lane order, through LDS; each
+// wave then walks whole rows group by group.  Of the nine operands of a
+// group only the three centre loads (one per tap row) are new: a wave keeps
+// the previous, current and next group of each tap row in registers and
+// forms the x -/+ D taps by shifting within the 16-lane rows (DPP) from the
+// current group and its left / right neighbour, so a group costs 3 loads
+// instead of 9.  The next-but-one group's loads are in flight while the
+// current group's 18 MFMAs run.  Points outside the grid load as zero.
+template <bool DGRAD, int D>
+__global__ __launch_bounds__(kThreads) void k_conv32(int B, int H, int W,
                                                      const bf16* __restrict__ X,
                                                      const float* __restrict__ prm, int ow, int ob,
                                                      const bf16* __restrict__ mask,
                                                      bf16* __restrict__ Y) {
+    static_assert(D >= 1 && D < 16, "taps must stay within a neighbouring group");
     __shared__ __attribute__((aligned(16))) bf16 wl[9 * 2 * 64 * 8];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m16 = lane & 15, kq = lane >> 4;
@@ -203,66 +243,76 @@ __global__ __launch_bounds__(kThreads) void k_conv32(int B, int H, int W, int d,
         for (int e = 0; e < 4; ++e) bias[h][e] = DGRAD ? 0.f : prm[ob + h * 16 + kq * 4 + e];
 
     const int gpr = (W + 15) / 16;
-    const long long ngroups = (long long)B * H * gpr;
+    const long long nrows = (long long)B * H;
     const long long nwaves = (long long)gridDim.x * 4;
-    // the nine 16-byte gathers of group gg (zero outside the grid)
-    auto gather = [&](long long gg, bf16x8(&dst)[9]) {
-        const int gx = (int)(gg % gpr);
-        const long long row = gg / gpr;  // b * H + y
-        const int y = (int)(row % H);
-        const long long sbase = (row - y) * W;
-        const int px = gx * 16 + m16;
+    bf16x8 zero8;
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int yy = y + (tap / 3 - 1) * d, xx = px + (tap % 3 - 1) * d;
-            if (inside(yy, xx, H, W)) {
-                dst[tap] = *reinterpret_cast<const bf16x8*>(
-                    X + (sbase + (long long)yy * W + xx) * CH + kq * 8);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) dst[tap][e] = (bf16)0.f;
-            }
-        }
+    for (int e = 0; e < 8; ++e) zero8[e] = (bf16)0.f;
+    // the 16-byte load of point px of input row yy (zero outside the grid)
+    auto load = [&](long long sbase, int yy, int px) {
+        bf16x8 v = zero8;
+        if (inside(yy, px, H, W))
+            v = *reinterpret_cast<const bf16x8*>(X + (sbase + (long long)yy * W + px) * CH + kq * 8);
+        return v;
     };
-    long long g = (long long)xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
-    bf16x8 bn[9];
-    if (g < ngroups) gather(g, bn);
-    for (; g < ngroups; g += nwaves) {
-        bf16x8 bv[9];
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) bv[tap] = bn[tap];
-        if (g + nwaves < ngroups) gather(g + nwaves, bn);
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tap][0], bv[tap], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[tap][1], bv[tap], acc1, 0, 0, 0);
-        }
-        const int gx = (int)(g % gpr);
-        const long long row = g / gpr;
+    for (long long row = (long long)xcd_remap(blockIdx.x, gridDim.x) * 4 + wv; row < nrows;
+         row += nwaves) {
         const int y = (int)(row % H);
         const long long sbase = (row - y) * W;
-        const int px = gx * 16 + m16;
-        if (px < W) {
-            const long long o = (sbase + (long long)y * W + px) * CH;
-            bf16x4 r0, r1;
-            if (DGRAD) {
-                const bf16x4 m0 = *reinterpret_cast<const bf16x4*>(mask + o + kq * 4);
-                const bf16x4 m1 = *reinterpret_cast<const bf16x4*>(mask + o + 16 + kq * 4);
+        // tap row r (dy = r - 1): previous, current and next group
+        bf16x8 P[3], C[3], N[3];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    r0[e] = (bf16)((float)m0[e] > 0.f ? acc0[e] : 0.f);
-                    r1[e] = (bf16)((float)m1[e] > 0.f ? acc1[e] : 0.f);
-                }
-            } else {
+        for (int r = 0; r < 3; ++r) {
+            P[r] = zero8;
+            C[r] = load(sbase, y + (r - 1) * D, m16);
+            N[r] = load(sbase, y + (r - 1) * D, 16 + m16);
+        }
+        for (int gx = 0; gx < gpr; ++gx) {
+            bf16x8 NN[3];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    r0[e] = (bf16)fmaxf(acc0[e] + bias[0][e], 0.f);
-                    r1[e] = (bf16)fmaxf(acc1[e] + bias[1][e], 0.f);
-                }
+            for (int r = 0; r < 3; ++r) NN[r] = load(sbase, y + (r - 1) * D, (gx + 2) * 16 + m16);
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                // x - D: this group's lane m16 - D, or the previous group's lane m16 - D + 16
+                const bf16x8 bl = sel8(m16 >= D, row_from_left<D>(C[r]), row_from_right<16 - D>(P[r]));
+                // x + D: this group's lane m16 + D, or the next group's lane m16 + D - 16
+                const bf16x8 br = sel8(m16 + D < 16, row_from_right<D>(C[r]), row_from_left<16 - D>(N[r]));
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 0][0], bl, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 0][1], bl, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 1][0], C[r], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 1][1], C[r], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 2][0], br, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[r * 3 + 2][1], br, acc1, 0, 0, 0);
             }
-            *reinterpret_cast<bf16x4*>(Y + o + kq * 4) = r0;
-            *reinterpret_cast<bf16x4*>(Y + o + 16 + kq * 4) = r1;
+            const int px = gx * 16 + m16;
+            if (px < W) {
+                const long long o = (sbase + (long long)y * W + px) * CH;
+                bf16x4 r0, r1;
+                if (DGRAD) {
+                    const bf16x4 m0 = *reinterpret_cast<const bf16x4*>(mask + o + kq * 4);
+                    const bf16x4 m1 = *reinterpret_cast<const bf16x4*>(mask + o + 16 + kq * 4);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        r0[e] = (bf16)((float)m0[e] > 0.f ? acc0[e] : 0.f);
+                        r1[e] = (bf16)((float)m1[e] > 0.f ? acc1[e] : 0.f);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        r0[e] = (bf16)fmaxf(acc0[e] + bias[0][e], 0.f);
+                        r1[e] = (bf16)fmaxf(acc1[e] + bias[1][e], 0.f);
+                    }
+                }
+                *reinterpret_cast<bf16x4*>(Y + o + kq * 4) = r0;
+                *reinterpret_cast<bf16x4*>(Y + o + 16 + kq * 4) = r1;
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                P[r] = C[r];
+                C[r] = N[r];
+                N[r] = NN[r];
+            }
         }
     }
 }
@@ -872,9 +922,9 @@ void forward(hipStream_t st, int B, int H, int W, const float* prm, const float*
                        (const bf16x2*)b.a0, prm, b.a1);
     const long long groups = (long long)B * H * ((W + 15) / 16);
     const unsigned cg = (unsigned)conv_grid(groups);
-    hipLaunchKernelGGL(k_conv32<false>, dim3(cg), dim3(kThreads), 0, st, B, H, W, DIL2,
+    hipLaunchKernelGGL((k_conv32<false, DIL2>), dim3(cg), dim3(kThreads), 0, st, B, H, W,
                        (const bf16*)b.a1, prm, OW2, OB2, (const bf16*)nullptr, b.a2);
-    hipLaunchKernelGGL(k_conv32<false>, dim3(cg), dim3(kThreads), 0, st, B, H, W, DIL3,
+    hipLaunchKernelGGL((k_conv32<false, DIL3>), dim3(cg), dim3(kThreads), 0, st, B, H, W,
                        (const bf16*)b.a2, prm, OW3, OB3, (const bf16*)nullptr, b.a3);
     hipLaunchKernelGGL(k_conv_out, dim3(pix_blocks(npix)), dim3(kThreads), 0, st, B, H, W,
                        (const bf16*)b.a3, prm, b.out, (const double*)b.frms, scale, x0);
@@ -908,13 +958,13 @@ void backward(hipStream_t st, int B, int H, int W, const float* prm, const Bufs&
                        (const bf16*)b.gA, (const bf16*)b.a2, b.part);
     hipLaunchKernelGGL(k_reduce_parts, dim3(rb), dim3(kThreads), 0, st, (const float*)b.part,
                        (int)wg, PS32, b.grad + OW3);
-    hipLaunchKernelGGL(k_conv32<true>, dim3(cg), dim3(kThreads), 0, st, B, H, W, DIL3,
+    hipLaunchKernelGGL((k_conv32<true, DIL3>), dim3(cg), dim3(kThreads), 0, st, B, H, W,
                        (const bf16*)b.gA, prm, OW3, 0, (const bf16*)b.a2, b.gB);
     hipLaunchKernelGGL(k_wgrad32, dim3(wg), dim3(kThreads), 0, st, B, H, W, DIL2,
                        (const bf16*)b.gB, (const bf16*)b.a1, b.part);
     hipLaunchKernelGGL(k_reduce_parts, dim3(rb), dim3(kThreads), 0, st, (const float*)b.part,
                        (int)wg, PS32, b.grad + OW2);
-    hipLaunchKernelGGL(k_conv32<true>, dim3(cg), dim3(kThreads), 0, st, B, H, W, DIL2,
+    hipLaunchKernelGGL((k_conv32<true, DIL2>), dim3(cg), dim3(kThreads), 0, st, B, H, W,
                        (const bf16*)b.gB, prm, OW2, 0, (const bf16*)b.a1, b.gA);
     // layer 1 (gA = dL/dz1)
     hipLaunchKernelGGL(k_wgrad_in, dim3((unsigned)tg), dim3(kThreads), 0, st, B, H, W, chunk,
