@@ -124,9 +124,8 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(int B, int H, int W,
                                                       const bf16x2* __restrict__ a0,
                                                       const float* __restrict__ prm,
                                                       bf16* __restrict__ a1) {
-    __shared__ float w[PS1];
-    for (int i = threadIdx.x; i < PS1; i += kThreads) w[i] = prm[OW1 + i];
-    __syncthreads();
+    // uniform weights: scalar loads (each output channel's 18 are contiguous)
+    const float* __restrict__ w = prm + OW1;
     const long long npix = (long long)B * H * W;
     const long long pix = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (pix >= npix) return;
@@ -325,9 +324,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_out(int B, int H, int W,
                                                        float* __restrict__ out,
                                                        const double* __restrict__ frms,
                                                        double scale, double* __restrict__ x0) {
-    __shared__ float w[PS4];
-    for (int i = threadIdx.x; i < PS4; i += kThreads) w[i] = prm[OW4 + i];
-    __syncthreads();
+    // the weights are uniform across the workgroup: scalar loads, one tap's
+    // 32 at a time, feed the FMAs as scalar operands
+    const float* __restrict__ w = prm + OW4;
     const long long hw = (long long)H * W, npix = B * hw;
     const long long pix = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (pix >= npix) return;
