@@ -115,6 +115,27 @@ def test_batched_gram_column_tiles_match_oracle(s, gram_cols, team):
         assert abs(info.iters - res.iters) <= max(2, res.iters // 10), (info.iters, res.iters)
 
 
+@pytest.mark.parametrize("team", [1, 2])
+def test_batched_thin_grids_match_oracle(team):
+    # grids whose rows are 1, 2, 3 or 5 points wide (the stencil's point pairs
+    # straddle rows) or a single row, 2-D and 3-D, the large one solved by a
+    # team: a fixed number of blocks against the oracle's iterates
+    probs = [PB.convdiff(2, 1, 10.0, seed=1600, ny=200), PB.convdiff(2, 2, 30.0, seed=1601, ny=150),
+             PB.convdiff(2, 3, 5.0, seed=1602, ny=121), PB.convdiff(2, 5, 60.0, seed=1603, ny=64),
+             PB.convdiff(2, 257, 20.0, seed=1604, ny=1),
+             PB.convdiff(3, 3, 40.0, seed=1605, ny=100, nz=120)]
+    fs = [O.apply(operator(p), p.x_true()) for p in probs]
+    status, infos, xs = run_batch(probs, fs, 4, 5, 0.0, max_iters=8, threads=512, team=team)
+    for p, f, x, info in zip(probs, fs, xs, infos):
+        xo, res = O.sgmres(operator(p), f, np.zeros(p.N), 4, 5, 0.0, max_blocks=8)
+        if res.status == O.OK:   # a small system may be solved exactly before 8 blocks
+            assert info.status == S.OK
+            continue
+        assert info.iters == res.iters == 8 and info.cycles == res.cycles
+        assert rel(x, xo) <= 1e-8, (p.nx, p.ny, rel(x, xo))
+    assert infos[-1].matvecs == team   # 36 000 points: a team when teams are on
+
+
 def test_batched_graph_replays_are_identical():
     probs, fs = make_batch(SIZES, GAMMAS, seed0=700)
     st = [S.Stencil.from_problem(p) for p in probs]
