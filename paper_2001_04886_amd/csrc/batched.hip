@@ -714,6 +714,92 @@ __device__ void wg_gram(const double* X, long long ldx, int ncx, const double* Z
     }
 }
 
+// Symmetric block Gram out[a * k + b] = sum_{p in R} Y[:, a][p] Y[:, b][p]
+// (a, b < k <= KMAX), every column read once (the general Gram would read
+// each column twice, as X and as Z).  Threads own point pairs (16-byte loads,
+// 2 NT points apart; with KMAX <= 5 the next pair's columns load while the
+// current pair's products are summed) and keep the upper triangle; the sums
+// are reduced over each wave, then over the waves in wave order through
+// scratch, an LDS area of NT / 64 * KMAX (KMAX + 1) / 2 doubles.  Columns past
+// k are clamped to valid ones and their sums dropped.  Out of line, like the
+// stencil pass, so its registers do not push the solve's state into scratch
+// inside the other streaming loops.
+template <int NT, int KMAX>
+__device__ __noinline__ void wg_gram_sym(const double* Y, long long ld, int k, const Range& R, double* out,
+                            double* scratch) {
+    constexpr int NT2 = KMAX * (KMAX + 1) / 2;
+    constexpr bool PF = KMAX <= 5;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    SSTEP_LDS double* sc = (SSTEP_LDS double*)scratch;
+    const double* yc[KMAX];
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) yc[c] = Y + (long long)(c < k ? c : k - 1) * ld;
+    double acc[NT2];
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) acc[t] = 0.0;
+    auto accum = [&](const d2v (&v)[KMAX]) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+            for (int b = a; b < KMAX; ++b, ++t)
+                acc[t] = fma(v[a].y, v[b].y, fma(v[a].x, v[b].x, acc[t]));
+    };
+    long long p = R.pa + 2 * (long long)threadIdx.x;
+    if constexpr (PF) {
+        d2v cur[KMAX], nxt[KMAX];
+        if (p < R.pb) {
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) cur[c] = ld2(yc[c] + p);
+        }
+        for (; p < R.pb; p += 2 * NT) {
+            const long long pn = p + 2 * NT;
+            if (pn < R.pb) {
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) nxt[c] = ld2(yc[c] + pn);
+            }
+            accum(cur);
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) cur[c] = nxt[c];
+        }
+    } else {
+        for (; p < R.pb; p += 2 * NT) {
+            d2v v[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) v[c] = ld2(yc[c] + p);
+            accum(v);
+        }
+    }
+    // the (at most two) single points of the range
+    const long long pe = threadIdx.x == 0 ? R.e0 : (threadIdx.x == 1 ? R.e1 : -1);
+    if (pe >= 0) {
+        double v[KMAX];
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) v[c] = ldg(yc[c] + pe);
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a)
+#pragma unroll
+            for (int b = a; b < KMAX; ++b, ++t) acc[t] = fma(v[a], v[b], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT2; ++t) {
+        const double w = wave_sum(acc[t]);
+        if (lane == 0) sc[wave * NT2 + t] = w;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < k * k; q += NT) {
+        const int a = q / k, b = q % k;
+        const int i = a < b ? a : b, j = a < b ? b : a;
+        const int t = i * KMAX - i * (i - 1) / 2 + (j - i);
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) sum += sc[w * NT2 + t];
+        out[a * k + b] = sum;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // one-thread FP64 scalar steps (kept out of line so that their registers do
 // not weigh on the streaming loops)
@@ -893,9 +979,9 @@ __device__ void solve_sys(const BatchArgs& args, BatchSys& S, BatchSlot& W, cons
             // block Gram of [w_k, y_1..y_s]
             {
                 double* gout = tm.T == 1 ? W.C : W.part[tm.parity];
-                // s + 1 columns of X: one pass with one (s + 1 <= NT / 64) or two per wave
-                constexpr int CB = (KZ + 1) <= NT / 64 ? 1 : 2;
-                wg_gram<NT, KZ + 1, CB>(Yk, ld, s1, Yk, ld, s1, R, gout, ztile);
+                // symmetric: each column read once; the Z-tile area is the
+                // reduction scratch (free between the Gram passes)
+                wg_gram_sym<NT, KZ + 1>(Yk, ld, s1, R, gout, reinterpret_cast<double*>(ztile));
                 if (tm.T > 1) team_combine<NT>(tm, W, s1 * s1, W.C);
             }
             pc.lap(SSTEP_K_GRAM);
