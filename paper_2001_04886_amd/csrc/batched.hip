@@ -1119,6 +1119,9 @@ template <int NT, int GC, int KZ>
 __global__ __launch_bounds__(NT) void k_batched_gmres(BatchArgs args) {
     __shared__ double red[NT / 64];
     __shared__ d2v ztile[gram_ztile_pairs<KZ + 1>()];
+    // the symmetric block Gram reduces its per-wave sums through this area
+    static_assert((NT / 64) * (KZ + 1) * (KZ + 2) / 2 * sizeof(double) <= sizeof(ztile),
+                  "Z-tile area too small for the symmetric Gram's reduction");
     __shared__ double sh[3 * kMaxS + 4];
     __shared__ double lw[kMaxS * kMaxS];
     __shared__ GramFactor lf;
