@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace sstep {
 
@@ -164,8 +165,12 @@ __device__ __forceinline__ void load_pts(const T* __restrict__ p, T (&v)[PPT]) {
         for (int e = 0; e < E; ++e) v[q * E + e] = t[e];
     }
 }
+// The store goes through an explicit global-address-space pointer and p has
+// no __restrict__: otherwise the compiler's rewriting of the inlined store
+// can drop its non-temporal bit (a plain global_store; block updates measured
+// 3-9% slower).
 template <typename T, int PPT>
-__device__ __forceinline__ void store_pts_nt(T* __restrict__ p, const T (&v)[PPT]) {
+__device__ __forceinline__ void store_pts_nt(T* p, const T (&v)[PPT]) {
     constexpr int E = 16 / sizeof(T);
     typedef T vt __attribute__((ext_vector_type(E)));
 #pragma unroll
@@ -173,7 +178,7 @@ __device__ __forceinline__ void store_pts_nt(T* __restrict__ p, const T (&v)[PPT
         vt t;
 #pragma unroll
         for (int e = 0; e < E; ++e) t[e] = v[q * E + e];
-        __builtin_nontemporal_store(t, reinterpret_cast<vt*>(p + q * E));
+        __builtin_nontemporal_store(t, (__attribute__((address_space(1))) vt*)(p + q * E));
     }
 }
 template <typename T, int PPT>
@@ -426,10 +431,16 @@ __global__ __launch_bounds__(UT) void k_update(
         }
 #pragma unroll
         for (int l = 0; l < NOUT; ++l) {
-            TO t[PPT];
+            // stored straight from the accumulators: a local copy in between
+            // lets the compiler drop the non-temporal bit when NOUT = 1
+            if constexpr (std::is_same_v<TA, TO>) {
+                store_pts_nt<TO, PPT>(out + l * ldo + p, acc[l]);
+            } else {
+                TO t[PPT];
 #pragma unroll
-            for (int e = 0; e < PPT; ++e) t[e] = (TO)acc[l][e];
-            store_pts_nt<TO, PPT>(out + l * ldo + p, t);
+                for (int e = 0; e < PPT; ++e) t[e] = (TO)acc[l][e];
+                store_pts_nt<TO, PPT>(out + l * ldo + p, t);
+            }
         }
         if (NORM) {
 #pragma unroll

@@ -739,18 +739,16 @@ inline void launch_update(Ctx& c, long long N, const TB* base, long long ldb, co
                           long long ldo, int nout, double* part, const int* skip, double bytes,
                           int cls = SSTEP_K_UPDATE) {
     c.begin(cls, bytes);
-    // 2-wave workgroups stream the basis slightly faster (measured 5.71 vs
-    // 5.55 TB/s for 312 -> 8 columns of 2^24 doubles); the norm partials
-    // keep the 4-wave shape their count is sized for
-    constexpr int UT = NORM ? kThreads : 128;
+    // 4-wave workgroups: with non-temporal output stores they stream 0.5-1.5%
+    // faster than 2-wave ones at every width from 40 to 312 columns (8 outputs
+    // of 2^24 doubles)
+    constexpr int UT = kThreads;
     const dim3 g((unsigned)((N + (long long)UT * update_ppt<TV, TB, TO>() - 1) /
                             ((long long)UT * update_ppt<TV, TB, TO>())));
 #define SSTEP_UPD(K)                                                                         \
     case K:                                                                                  \
-        hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM && (K == 1), (NORM && K == 1) ? kThreads : UT>), \
-                           (NORM && K == 1) ? dim3((unsigned)update_blocks_t<TV, TB, TO>(N)) : g,       \
-                           dim3((NORM && K == 1) ? kThreads : UT), 0, c.st, N, base, ldb, V, ldv, n2,   \
-                           n2_dev, M, out, ldo, part, skip);                                 \
+        hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM && (K == 1), UT>), g, dim3(UT), 0, \
+                           c.st, N, base, ldb, V, ldv, n2, n2_dev, M, out, ldo, part, skip);  \
         break;
     switch (nout) {
         SSTEP_UPD(1) SSTEP_UPD(2) SSTEP_UPD(3) SSTEP_UPD(4) SSTEP_UPD(5) SSTEP_UPD(6)
