@@ -741,14 +741,28 @@ inline void launch_update(Ctx& c, long long N, const TB* base, long long ldb, co
     c.begin(cls, bytes);
     // 4-wave workgroups: with non-temporal output stores they stream 0.5-1.5%
     // faster than 2-wave ones at every width from 40 to 312 columns (8 outputs
-    // of 2^24 doubles)
-    constexpr int UT = kThreads;
-    const dim3 g((unsigned)((N + (long long)UT * update_ppt<TV, TB, TO>() - 1) /
-                            ((long long)UT * update_ppt<TV, TB, TO>())));
+    // of 2^24 doubles).  FP64 updates of 4 or more outputs against 128 or more
+    // stored columns take 16-wave workgroups: 2.3-2.7% faster at 160 and 312
+    // columns, even at 80 and 7% slower at 40.
+    constexpr int UT = kThreads, UTW = 1024;
+    const bool wide = !NORM && sizeof(TV) == 8 && n2 >= 128;
+    const auto grid = [&](int ut) {
+        const long long per = (long long)ut * update_ppt<TV, TB, TO>();
+        return dim3((unsigned)((N + per - 1) / per));
+    };
 #define SSTEP_UPD(K)                                                                         \
     case K:                                                                                  \
-        hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM && (K == 1), UT>), g, dim3(UT), 0, \
-                           c.st, N, base, ldb, V, ldv, n2, n2_dev, M, out, ldo, part, skip);  \
+        if constexpr (K >= 4 && !NORM && sizeof(TV) == 8) {                                  \
+            if (wide) {                                                                      \
+                hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, false, UTW>), grid(UTW),     \
+                                   dim3(UTW), 0, c.st, N, base, ldb, V, ldv, n2, n2_dev, M,  \
+                                   out, ldo, part, skip);                                    \
+                break;                                                                       \
+            }                                                                                \
+        }                                                                                    \
+        hipLaunchKernelGGL((k_update<TV, TB, TO, TA, K, NORM && (K == 1), UT>), grid(UT),    \
+                           dim3(UT), 0, c.st, N, base, ldb, V, ldv, n2, n2_dev, M, out, ldo, \
+                           part, skip);                                                      \
         break;
     switch (nout) {
         SSTEP_UPD(1) SSTEP_UPD(2) SSTEP_UPD(3) SSTEP_UPD(4) SSTEP_UPD(5) SSTEP_UPD(6)

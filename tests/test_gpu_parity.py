@@ -134,7 +134,8 @@ def test_block_self_gram_matches_numpy(N, nc):
 
 
 @pytest.mark.parametrize("N,ncx,ncy", [(1, 1, 1), (999, 0, 3), (4097, 40, 8), (100003, 13, 16),
-                                       (1 << 20, 64, 1), (511, 5, 1), (512, 6, 9), (513, 7, 2)])
+                                       (1 << 20, 64, 1), (511, 5, 1), (512, 6, 9), (513, 7, 2),
+                                       (2047, 128, 5), (2049, 130, 16), (100003, 201, 8)])
 def test_block_update_matches_numpy(N, ncx, ncy):
     rng = np.random.default_rng(N + ncx)
     ld = (N + 63) // 64 * 64

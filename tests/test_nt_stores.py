@@ -39,12 +39,14 @@ def test_update_output_stores_are_nontemporal(tmp_path):
     for tv, tb, to, ta in COMBOS:
         for k in range(1, 17):
             for norm in ((False, True) if k == 1 else (False,)):
-                nb = "true" if norm else "false"
-                lines.append(
-                    f"template __global__ void k_update<{tv}, {tb}, {to}, {ta}, {k}, {nb}, 256>("
-                    f"long long, const {tb}*, long long, const {tv}*, long long, int, const int*, "
-                    f"const double*, {to}*, long long, double*, const int*);")
-                cases.append((tv, tb, to, ta, k, norm))
+                # 16-wave workgroups: FP64 updates of 4 or more outputs
+                for ut in ((256, 1024) if (k >= 4 and tv == "double") else (256,)):
+                    nb = "true" if norm else "false"
+                    lines.append(
+                        f"template __global__ void k_update<{tv}, {tb}, {to}, {ta}, {k}, {nb}, {ut}>("
+                        f"long long, const {tb}*, long long, const {tv}*, long long, int, const int*, "
+                        f"const double*, {to}*, long long, double*, const int*);")
+                    cases.append((tv, tb, to, ta, k, norm, ut))
     lines.append("}")
     src = tmp_path / "update_inst.hip"
     src.write_text("\n".join(lines) + "\n")
@@ -60,8 +62,8 @@ def test_update_output_stores_are_nontemporal(tmp_path):
         end = text.index(".Lfunc_end", m.end())
         bodies[m.group(1)] = text[m.end():end]
     checked = 0
-    for tv, tb, to, ta, k, norm in cases:
-        key = f"I{MANGLE[tv]}{MANGLE[tb]}{MANGLE[to]}{MANGLE[ta]}Li{k}ELb{int(norm)}ELi256E"
+    for tv, tb, to, ta, k, norm, ut in cases:
+        key = f"I{MANGLE[tv]}{MANGLE[tb]}{MANGLE[to]}{MANGLE[ta]}Li{k}ELb{int(norm)}ELi{ut}E"
         names = [n for n in bodies if key in n]
         assert len(names) == 1, (key, names)
         stores = re.findall(r"global_store_dwordx4[^\n]*", bodies[names[0]])
