@@ -339,13 +339,28 @@ static __global__ __launch_bounds__(kThreads) void k_gram_reduce(const double* _
         const int c = o / nz, jz = o % nz;
         const int per = (nchunk + 3) / 4;
         const int ch0 = qd * per, ch1 = min(nchunk, ch0 + per);
+        // even chunks into s0, odd ones into s1, each in chunk order; eight
+        // chunks' loads are issued before their sums (the order of the
+        // additions, and so the result, does not depend on the batching)
+        const long long str = (long long)ncx * KZ;
+        const double* pp = part + ((long long)ch0 * ncx + c) * KZ + jz;
         double s0 = 0.0, s1 = 0.0;
         int ch = ch0;
-        for (; ch + 1 < ch1; ch += 2) {
-            s0 += part[((long long)ch * ncx + c) * KZ + jz];
-            s1 += part[((long long)(ch + 1) * ncx + c) * KZ + jz];
+        for (; ch + 8 <= ch1; ch += 8, pp += 8 * str) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = pp[u * str];
+#pragma unroll
+            for (int u = 0; u < 8; u += 2) {
+                s0 += a[u];
+                s1 += a[u + 1];
+            }
         }
-        if (ch < ch1) s0 += part[((long long)ch * ncx + c) * KZ + jz];
+        for (; ch + 1 < ch1; ch += 2, pp += 2 * str) {
+            s0 += pp[0];
+            s1 += pp[str];
+        }
+        if (ch < ch1) s0 += pp[0];
         s = s0 + s1;
     }
     lds[qd][lo] = s;
