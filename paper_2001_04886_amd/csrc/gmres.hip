@@ -415,26 +415,92 @@ __global__ __launch_bounds__(64) void k_gm_givens(GmArrays a) {
 }
 
 // Least-squares solution y = R^{-1} rhs (eq. (8)) and assembly coefficients.
+// Back substitution over the columns of R, last first.  Thread t owns rows
+// t, t + kThreads, ... (ROWS of them) of the right-hand side, kept in
+// registers; the column
+// of step i is loaded kSolvePf steps ahead, so a step costs one barrier (the
+// owner of row i publishes y_i through LDS) instead of two dependent global
+// loads.  The barrier orders LDS only: a full __syncthreads() would also wait
+// for the columns in flight.  Each row is updated by the same operations in
+// the same order as a plain column-oriented back substitution.
+constexpr int kSolvePf = 4;  // columns of R in flight
+static_assert(8 * kThreads >= kMaxCols, "8 rows per thread must cover kMaxCols");
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+template <int ROWS>
 __global__ __launch_bounds__(kThreads) void k_gm_solve(GmArrays a) {
-    __shared__ double b[2048];
-    __shared__ double yi;
+    constexpr int kSolveRows = ROWS;  // rows per thread: ROWS * kThreads >= m * s
+    __shared__ double ypub[2];
     GmState* st = a.st;
     if (!st->active) return;
     const int n = st->ncols, s = st->s, ldg = st->ldg;
-    for (int i = threadIdx.x; i < n; i += kThreads) b[i] = a.rhs[i];
-    __syncthreads();
-    for (int i = n - 1; i >= 0; --i) {
-        if (threadIdx.x == 0) {
-            yi = b[i] / a.R[i + (long long)i * ldg];
-            a.y[i] = yi;
-        }
-        __syncthreads();
-        const double v = yi;
-        for (int r = threadIdx.x; r < i; r += kThreads) b[r] -= a.R[r + (long long)i * ldg] * v;
-        __syncthreads();
+    const int t = threadIdx.x;
+    double b[kSolveRows], yv[kSolveRows];
+#pragma unroll
+    for (int k = 0; k < kSolveRows; ++k) {
+        const int r = t + k * kThreads;
+        b[k] = r < n ? a.rhs[r] : 0.0;
+        yv[k] = 0.0;
     }
-    for (int c = threadIdx.x; c < n; c += kThreads)
-        a.coefA[c] = a.y[c] * ((c % s == 0) ? st->inv_nu[c / s] : 1.0);
+    // column i of R as this thread's rows r <= i (zeros elsewhere); every load
+    // is issued (out-of-range ones read R[0]), so the loads in flight can be
+    // counted and only the column a step uses is waited for
+    auto load_col = [&](int i, double (&dst)[kSolveRows]) {
+#pragma unroll
+        for (int k = 0; k < kSolveRows; ++k) {
+            const int r = t + k * kThreads;
+            const bool in = i >= 0 && r <= i;
+            const double x = a.R[in ? r + (long long)i * ldg : 0];
+            dst[k] = in ? x : 0.0;
+        }
+    };
+    // step i: the owner of row i forms y_i, every row r < i takes its share;
+    // then the slot refills with the column kSolvePf steps ahead
+    auto step = [&](int i, double (&c)[kSolveRows]) {
+        const int ko = i / kThreads;
+        if (t == i % kThreads) {
+            double bi = 0.0, di = 1.0;
+#pragma unroll
+            for (int k = 0; k < kSolveRows; ++k)
+                if (k == ko) {
+                    bi = b[k];
+                    di = c[k];
+                }
+            const double yi = bi / di;
+#pragma unroll
+            for (int k = 0; k < kSolveRows; ++k)
+                if (k == ko) yv[k] = yi;
+            ypub[i & 1] = yi;
+        }
+        lds_barrier();
+        const double v = ypub[i & 1];
+#pragma unroll
+        for (int k = 0; k < kSolveRows; ++k)
+            if (t + k * kThreads < i) b[k] -= c[k] * v;
+        load_col(i - kSolvePf, c);
+    };
+    double col[kSolvePf][kSolveRows];
+#pragma unroll
+    for (int u = 0; u < kSolvePf; ++u) load_col(n - 1 - u, col[u]);
+    int i = n - 1;
+    for (; i >= kSolvePf - 1; i -= kSolvePf) {  // whole groups of kSolvePf steps
+#pragma unroll
+        for (int u = 0; u < kSolvePf; ++u) step(i - u, col[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kSolvePf - 1; ++u)  // the last i + 1 < kSolvePf steps
+        if (i - u >= 0) step(i - u, col[u]);
+#pragma unroll
+    for (int k = 0; k < kSolveRows; ++k) {
+        const int r = t + k * kThreads;
+        if (r < n) {
+            a.y[r] = yv[k];
+            a.coefA[r] = yv[k] * ((r % s == 0) ? st->inv_nu[r / s] : 1.0);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -721,7 +787,15 @@ static void gmres_enqueue_cycle(Ctx& c, const StencilView& v, GmArrays& a, GmSta
         }
         c.cur_block = -1;
         c.begin(SSTEP_K_SCALAR, 0.0);
-        hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(kThreads), 0, c.st, a);
+        // rows per thread of the back substitution: enough for the m * s columns
+        if (K <= kThreads)
+            hipLaunchKernelGGL(k_gm_solve<1>, dim3(1), dim3(kThreads), 0, c.st, a);
+        else if (K <= 2 * kThreads)
+            hipLaunchKernelGGL(k_gm_solve<2>, dim3(1), dim3(kThreads), 0, c.st, a);
+        else if (K <= 4 * kThreads)
+            hipLaunchKernelGGL(k_gm_solve<4>, dim3(1), dim3(kThreads), 0, c.st, a);
+        else
+            hipLaunchKernelGGL(k_gm_solve<8>, dim3(1), dim3(kThreads), 0, c.st, a);
         SSTEP_HIP(hipGetLastError());
         c.end();
         // x = x0 + V y (eq. (8)); column count read on the device

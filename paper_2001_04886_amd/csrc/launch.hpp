@@ -742,10 +742,11 @@ inline void launch_update(Ctx& c, long long N, const TB* base, long long ldb, co
     // 4-wave workgroups: with non-temporal output stores they stream 0.5-1.5%
     // faster than 2-wave ones at every width from 40 to 312 columns (8 outputs
     // of 2^24 doubles).  FP64 updates of 4 or more outputs against 128 or more
-    // stored columns take 16-wave workgroups: 2.3-2.7% faster at 160 and 312
-    // columns, even at 80 and 7% slower at 40.
+    // stored columns on large grids take 16-wave workgroups: 2.3-2.7% faster at
+    // 160 and 312 columns, even at 80 and 7% slower at 40; on small grids (2^16
+    // points: 32 such workgroups) they are 45% slower.
     constexpr int UT = kThreads, UTW = 1024;
-    const bool wide = !NORM && sizeof(TV) == 8 && n2 >= 128;
+    const bool wide = !NORM && sizeof(TV) == 8 && n2 >= 128 && N >= (1LL << 22);
     const auto grid = [&](int ut) {
         const long long per = (long long)ut * update_ppt<TV, TB, TO>();
         return dim3((unsigned)((N + per - 1) / per));

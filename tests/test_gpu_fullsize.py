@@ -139,14 +139,16 @@ def test_block_self_gram_full():
     release()
 
 
-def test_block_update_full_sampled():
-    # Y[l] += sum_c X[c] M[c, l] with 312 columns into 8 at N = 2^24; 8192
-    # sampled rows (first and last tile included) recomputed by numpy within
-    # the standard rounding bound of a length-(ncx + 1) sum, counted for both
-    # sides
-    N, ncx, ncy = 1 << 24, 312, 8
-    X = _gen((ncx, N), 104)
-    Y = _gen((ncy, N), 105)
+@pytest.mark.parametrize("N,ncx,ncy", [(1 << 24, 312, 8), ((1 << 22) + 3, 130, 5)])
+def test_block_update_full_sampled(N, ncx, ncy):
+    # Y[l] += sum_c X[c] M[c, l] with 312 columns into 8 at N = 2^24 (and a
+    # ragged 2^22 + 3 with 130 into 5; both take the 16-wave workgroups of
+    # wide updates on large grids); 8192 sampled rows (first and last tile
+    # included) recomputed by numpy within the standard rounding bound of a
+    # length-(ncx + 1) sum, counted for both sides
+    ld = (N + 63) // 64 * 64  # column stride: 16-byte aligned columns
+    X = _gen((ncx, ld), 104)[:, :N]
+    Y = _gen((ncy, ld), 105)[:, :N]
     rng = np.random.default_rng(106)
     Mh = rng.standard_normal((ncx, ncy)) / ncx
     rows = np.unique(np.concatenate([np.arange(64), np.arange(N - 64, N),
